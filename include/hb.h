@@ -1,0 +1,214 @@
+/*
+ * hb.h -- C ABI of libhb, MI355X (gfx950) batch hashing: MD5, SHA-1 and SM3 digests of
+ * very many independent messages.
+ *
+ * The operation is the paper's multi-message ("parallel scenario") crypto op: many
+ * digests computed at once, each message and each digest in its own slot so the work is
+ * free of races (Sec. IV-B; Sec. V-D).  The digests themselves are defined by the
+ * standards the paper names: MD5 = RFC 1321, SHA-1 = FIPS 180-4, SM3 = GB/T 32905-2016.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every function returns an int status (HB_OK or a negative HB_E* code) and
+ *    never throws.  Argument errors are reported before anything is enqueued; the text of
+ *    the last error on the calling thread is available from hb_last_error().
+ *  - Execution is asynchronous on the given HIP stream (a hipStream_t passed as void*;
+ *    NULL means the legacy default stream), like hipMemcpyAsync.  A device fault surfaces
+ *    as HB_EHIP from a later call or synchronisation.
+ *  - Messages are bytes.  Message i is messages[offsets[i] .. offsets[i] + lengths[i]):
+ *    offsets may have any byte alignment, messages may overlap or leave gaps, and a length
+ *    of 0 is valid.  Lengths are below 2^61 bytes (the bit length must fit 64 bits).
+ *  - Digests are the canonical digest bytes (what the standards print): 16 bytes for MD5,
+ *    20 for SHA-1, 32 for SM3, digest i at digests_out + i * stride.  digests_out must be
+ *    4-byte aligned, must not overlap the inputs, and stride must be a multiple of 4 and
+ *    at least the digest size.  Bytes of a slot past the digest size are written as zero.
+ *  - Pointers named "device" are device memory (hipMalloc / torch CUDA tensors) owned by
+ *    the caller, which keeps them valid and unmodified until the stream work completes.
+ *    Pointers named "host" are host memory, also owned by the caller.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { HB_MD5 = 0, HB_SHA1 = 1, HB_SM3 = 2 };
+enum { HB_OK = 0, HB_EINVAL = -1, HB_ENOMEM = -2, HB_EHIP = -3, HB_EBUDGET = -4, HB_EBUSY = -5 };
+
+/* Digest size in bytes of algo (16, 20 or 32); 0 for an unknown id. */
+size_t hb_digest_size(int algo);
+
+/* Thread-local text describing the last non-OK status returned on this thread. */
+const char *hb_last_error(void);
+
+/* Library and device facts: CU count, wave size, peak engine clock (kHz) and gfx arch
+ * name of the current device.  Returns HB_EHIP if no device is visible. */
+int hb_device_info(int *cu_count, int *wave_size, int *clock_khz, char *arch_name, size_t arch_len);
+
+/*
+ * hash_batch -- plain batch hashing, one GPU lane per message, in index order.
+ *   algo         HB_MD5 / HB_SHA1 / HB_SM3
+ *   messages     device, packed message bytes
+ *   offsets      device, n x uint64 byte offsets into messages
+ *   lengths      device, n x uint64 message lengths in bytes
+ *   n            message count; 0 is a no-op returning HB_OK
+ *   digests_out  device, n slots of hb_digest_size(algo) bytes (stride = digest size)
+ *   stream       hipStream_t
+ * Allocates nothing, so it may be captured in a hipGraph.  The padding and the length
+ * field (RFC 1321 Sec. 3.1-3.2, FIPS 180-4 Sec. 5.1.1, GB/T 32905 Sec. 5.2) are built in
+ * registers; no padded copy of the input is made.
+ */
+int hash_batch(int algo, const uint8_t *messages, const uint64_t *offsets, const uint64_t *lengths,
+               uint64_t n, uint8_t *digests_out, void *stream);
+
+/* As hash_batch, with an explicit digest stride in bytes (multiple of 4, >= digest size). */
+int hash_batch_strided(int algo, const uint8_t *messages, const uint64_t *offsets,
+                       const uint64_t *lengths, uint64_t n, uint8_t *digests_out,
+                       uint64_t stride, void *stream);
+
+/*
+ * hash_batch_fixed -- n messages of exactly msg_len bytes stored back to back:
+ * message i is messages[i * msg_len .. (i + 1) * msg_len).  No metadata arrays are read.
+ * digests_out holds n slots of hb_digest_size(algo) bytes.  Allocates nothing.
+ */
+int hash_batch_fixed(int algo, const uint8_t *messages, uint64_t n, uint64_t msg_len,
+                     uint8_t *digests_out, void *stream);
+
+/*
+ * hash_batch_mixed -- each message with its own algorithm, plain form: one launch per
+ * algorithm present, each lane skipping messages of the other algorithms.
+ *   algos        device, n x uint8 algorithm ids
+ *   digests_out  device, n slots of 32 bytes (bytes past the digest size are zeroed)
+ * An invalid id in algos is not detected on the device; its slot is left all zero.
+ * Allocates nothing.
+ */
+int hash_batch_mixed(const uint8_t *algos, const uint8_t *messages, const uint64_t *offsets,
+                     const uint64_t *lengths, uint64_t n, uint8_t *digests_out, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Batched form: length-bucketed, longest-first, persistent fused launch in a hipGraph.  */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct hb_plan hb_plan;
+
+enum {
+    HB_PLAN_GRAPH = 1,      /* capture the pipeline in a hipGraph and replay it (default on) */
+    HB_PLAN_AUTOTUNE = 2,   /* time the kernel variants on first use and cache the choice */
+    HB_PLAN_NO_SORT = 4     /* skip bucketing: lanes take messages in index order */
+};
+
+/*
+ * hb_plan_create -- reserve device workspace for batches of up to max_n messages and
+ * build the launch plan.  The plan owns its workspace (about 24 bytes per message plus
+ * a fixed part) and, with HB_PLAN_GRAPH, a hipGraph captured on first run.
+ * Returns HB_ENOMEM if the workspace cannot be allocated.
+ */
+int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags);
+
+/*
+ * hb_plan_run -- hash n <= max_n messages.  algos (device, n x uint8) gives per-message
+ * algorithm ids; when algos is NULL every message uses algo.  digests_out stride is 32
+ * bytes when algos != NULL, else hb_digest_size(algo).  Other arguments as hash_batch.
+ * The steps (all on the device, in stream order): per-message block count
+ * nb = floor((L + 8) / 64) + 1; counting sort by (algorithm, nb) descending; work items
+ * of one wave each (algorithm-uniform lanes of near-equal nb); items merged by estimated
+ * cost, longest first; one persistent launch whose waves pull items from an atomic queue.
+ * Calls on one plan are serialised by the caller (a plan is not thread-safe); the host
+ * waits for the previous run's parameter block to be consumed before reusing it.
+ */
+int hb_plan_run(hb_plan *plan, const uint8_t *algos, int algo, const uint8_t *messages,
+                const uint64_t *offsets, const uint64_t *lengths, uint64_t n,
+                uint8_t *digests_out, void *stream);
+
+/* Launch choices of a plan (after autotuning, if enabled). */
+int hb_plan_config(const hb_plan *plan, int *waves_per_cu, int *msgs_per_lane, int *variant);
+
+/* Force launch choices (0 keeps the current value); drops any captured graph. */
+int hb_plan_set_config(hb_plan *plan, int waves_per_cu, int msgs_per_lane, int variant);
+
+/* Average duration in milliseconds of the persistent hashing kernel over the runs since
+ * the last call, measured with HIP events around it on the plan's stream; -1 if none. */
+double hb_plan_kernel_ms(hb_plan *plan);
+
+void hb_plan_destroy(hb_plan *plan);
+
+/* ------------------------------------------------------------------------------------ */
+/* Host-resident inputs: chunked H2D copies overlapped with hashing.                      */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * hash_batch_host -- hash messages that live in host memory.  The messages are split into
+ * chunks of about chunk_bytes; chunk k+1 is copied into the device on a copy stream
+ * (through pinned staging) while chunk k is hashed on the compute stream, each hash
+ * launch gated by an event on its copy.  Digests are copied back to digests_out_host.
+ *   algos_host      host, n x uint8 per-message ids, or NULL to use algo
+ *   messages_host   host bytes; offsets_host/lengths_host host uint64 arrays
+ *   digests_out_host host, n slots (stride 32 with algos_host, else digest size)
+ * Blocking: returns when every digest is in digests_out_host.  Allocates device and
+ * pinned buffers on first use and keeps them for later calls (per thread).
+ */
+int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                    const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                    uint8_t *digests_out_host, uint64_t chunk_bytes);
+
+/* ------------------------------------------------------------------------------------ */
+/* Serving: continuous batching of hash requests under an HBM budget.                    */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct hb_server hb_server;
+
+/*
+ * hb_server_create -- start a serving loop on `device` with a device-memory budget of
+ * hbm_budget_bytes (request payload + metadata + digests resident at once) and at most
+ * max_slots requests in flight.  A background host thread admits queued requests in
+ * arrival order while both limits hold, stages each admitted request's bytes into the
+ * device on a copy stream, and launches hashing steps on rotating compute streams, so a
+ * request arriving while others run starts as soon as memory and a slot free up and its
+ * work overlaps theirs on the device.
+ */
+int hb_server_create(hb_server **server, int device, uint64_t hbm_budget_bytes, int max_slots);
+
+/*
+ * hb_server_submit -- queue one request (host pointers, valid until completion).
+ *   algo_or_mixed  an algorithm id, or -1 to use algos[] per message
+ *   algos          host n x uint8 ids when algo_or_mixed == -1, else ignored
+ *   digests_out    host, n slots (stride 32 when mixed, else digest size)
+ * Returns HB_EINVAL for malformed requests and HB_EBUDGET for a request that could never
+ * fit the budget; either fails alone.  On success *ticket identifies the request.
+ */
+int hb_server_submit(hb_server *server, int algo_or_mixed, const uint8_t *algos,
+                     const uint8_t *messages, const uint64_t *offsets, const uint64_t *lengths,
+                     uint64_t n, uint8_t *digests_out, uint64_t *ticket);
+
+/* Non-blocking completion check: *done = 1 when finished, with its status in *status. */
+int hb_server_poll(hb_server *server, uint64_t ticket, int *done, int *status);
+
+/* Block until the request completes (or timeout_ms elapses, -1 = forever: HB_EBUSY on
+ * timeout); *status receives its status. */
+int hb_server_wait(hb_server *server, uint64_t ticket, int64_t timeout_ms, int *status);
+
+/* Per-request timestamps in seconds on the server's steady clock: arrival (submit),
+ * admission, input resident on the device, digests ready on the host. */
+int hb_server_times(hb_server *server, uint64_t ticket, double *t_submit, double *t_admit,
+                    double *t_h2d_done, double *t_done);
+
+/* Counters: requests completed, device steps launched, admission stalls (a queued head
+ * request held back by the budget or slot limit), peak resident bytes. */
+int hb_server_stats(hb_server *server, uint64_t *completed, uint64_t *steps, uint64_t *stalls,
+                    uint64_t *peak_bytes);
+
+/* Current time on the server clock (seconds), for timestamps taken by the caller. */
+double hb_server_now(hb_server *server);
+
+/* Drain outstanding requests and stop the loop. */
+void hb_server_destroy(hb_server *server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

@@ -1,0 +1,25 @@
+// hb_internal.hpp -- host-side declarations shared by the libhb translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace hb {
+
+// Thread-local last-error text (exposed by hb_last_error) and the status it goes with.
+int set_error(int status, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+
+// Plain launches (one lane per message, index order).  `fixed` selects the contiguous
+// fixed-length layout (message i at i * fixed_len; offsets/lengths unused).  filter !=
+// nullptr hashes only the messages whose id equals algo (the MD5 launch also zeroes the
+// slots of invalid ids).  Returns the hipError_t of the launch.
+hipError_t launch_plain(int algo, const uint8_t *msgs, const uint64_t *offs, const uint64_t *lens,
+                        uint64_t n, bool fixed, uint64_t fixed_len, uint8_t *out, uint32_t stride,
+                        const uint8_t *filter, hipStream_t stream);
+
+int digest_size(int algo);
+
+}  // namespace hb

@@ -1,0 +1,738 @@
+// hb_plan.hip -- batched form: on-device bucketing by (algorithm, block count), work items
+// of one wave each ordered longest first, and one persistent fused launch whose waves pull
+// items from an atomic queue.  The pipeline is captured once in a hipGraph and replayed;
+// per-run pointers reach the captured kernels through a device-side parameter block that
+// a small kernel, launched ahead of the graph, fills from its own launch arguments.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_device.hpp"
+#include "hb_internal.hpp"
+
+namespace hb {
+
+// ---------------------------------------------------------------------------------------
+// Layout constants
+// ---------------------------------------------------------------------------------------
+
+constexpr uint32_t kBins = 16448;      // block-count keys per algorithm: key = min(nb, kBins - 1)
+constexpr uint32_t kLdsKeys = 1024;    // keys below this are counted in LDS first
+constexpr uint32_t kInvalid = 0xffffffffu;
+constexpr int kThreads = 256;          // 4 waves per workgroup
+constexpr int kScanThreads = 1024;
+constexpr int kMaxMpl = 4;             // messages per lane per work item, at most
+
+// VALU ops per 64-byte block of each algorithm (the compression plus word loads), used to
+// weigh work items of different algorithms against each other.
+__host__ __device__ constexpr uint32_t algo_cost(int a) { return a == 0 ? 340u : (a == 1 ? 620u : 1350u); }
+
+// Run parameters, written on the device before each run (see k_set_desc).
+struct PlanDesc {
+    const uint8_t *algos;     // per-message ids, or nullptr
+    const uint8_t *msgs;
+    const uint64_t *offs;
+    const uint64_t *lens;
+    uint8_t *out;
+    uint64_t n;
+    uint32_t stride;
+    int32_t algo;             // used when algos == nullptr
+    int32_t sort;             // 0: one key per algorithm (index order within it)
+    int32_t mpl;              // messages per lane per item
+};
+
+// Meta block (device): segment bookkeeping filled by k_scan / k_items.
+struct PlanMeta {
+    uint32_t count[3];        // messages per algorithm
+    uint32_t seg_pos[4];      // first sorted position of each algorithm's segment (+ end)
+    uint32_t seg_item[4];     // first item of each segment (+ total)
+    uint32_t queue;           // next item to hand out
+    uint32_t pad;
+    unsigned long long total_cost;
+};
+
+// Device workspace (pointers fixed for the plan's life).
+struct PlanWs {
+    PlanDesc *desc;
+    PlanMeta *meta;
+    uint32_t *hist;           // 3 * kBins counts
+    uint32_t *cursor;         // 3 * kBins running positions
+    uint32_t *bin_start;      // 3 * kBins first sorted position of each key
+    uint32_t *sorted;         // message indices, per-algorithm segments, padded to items
+    uint32_t *order;          // item ids, longest first
+    uint64_t max_n;
+};
+
+__device__ __forceinline__ uint32_t msg_key(uint64_t len, int sort)
+{
+    if (!sort) return 0;
+    const uint64_t nb = (len + 8u) / 64u + 1u;
+    return nb >= kBins ? kBins - 1 : uint32_t(nb);
+}
+
+__device__ __forceinline__ int msg_algo(const PlanDesc &d, uint64_t i)
+{
+    return d.algos ? int(d.algos[i]) : d.algo;
+}
+
+__device__ __forceinline__ uint64_t lane_mask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// ---------------------------------------------------------------------------------------
+// Pipeline kernels
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_set_desc(PlanDesc d, PlanDesc *dst) { *dst = d; }
+
+// Clear counts, cursors and the queue (a kernel, so the graph holds no memset node).
+__global__ __launch_bounds__(kThreads) void k_zero(PlanWs ws)
+{
+    const uint32_t t = blockIdx.x * kThreads + threadIdx.x, step = gridDim.x * kThreads;
+    for (uint32_t i = t; i < 3 * kBins; i += step) { ws.hist[i] = 0; ws.cursor[i] = 0; }
+    if (t == 0) {
+        PlanMeta *m = ws.meta;
+        for (int a = 0; a < 3; ++a) m->count[a] = 0;
+        m->queue = 0;
+        m->total_cost = 0;
+    }
+}
+
+// Histogram of keys per algorithm.  Invalid ids are not counted (their slot is zeroed by
+// k_zero_invalid).  Wave-uniform keys take one LDS atomic per wave.
+__global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
+{
+    __shared__ uint32_t lh[3 * kLdsKeys];
+    const PlanDesc d = *ws.desc;
+    for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) lh[i] = 0;
+    __syncthreads();
+    const uint64_t step = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t base = uint64_t(blockIdx.x) * kThreads; base < d.n; base += step) {
+        const uint64_t i = base + threadIdx.x;
+        if (i < d.n) {
+            const int a = msg_algo(d, i);
+            if (a >= 0 && a < 3) {
+                const uint32_t key = msg_key(d.lens[i], d.sort);
+                const uint32_t slot = uint32_t(a) * kBins + key;
+                const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
+                const uint64_t same = __ballot(slot == first);
+                const uint64_t active = __ballot(1);
+                if (same == active && key < kLdsKeys) {
+                    if ((active & lane_mask_lt()) == 0)
+                        atomicAdd(&lh[uint32_t(a) * kLdsKeys + key], uint32_t(__popcll(active)));
+                } else if (key < kLdsKeys) {
+                    atomicAdd(&lh[uint32_t(a) * kLdsKeys + key], 1u);
+                } else {
+                    atomicAdd(&ws.hist[slot], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) {
+        const uint32_t c = lh[i];
+        if (c) atomicAdd(&ws.hist[(i / kLdsKeys) * kBins + (i % kLdsKeys)], c);
+    }
+}
+
+// Exclusive scan, longest key first within each algorithm; segments padded to whole
+// items (64 * mpl positions) whose padding slots hold kInvalid.
+__global__ __launch_bounds__(kScanThreads) void k_scan(PlanWs ws)
+{
+    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint32_t seg_base;
+    const PlanDesc d = *ws.desc;
+    const uint32_t per_item = 64u * uint32_t(d.mpl);
+    constexpr uint32_t kPer = (kBins + kScanThreads - 1) / kScanThreads;
+    if (threadIdx.x == 0) seg_base = 0;
+    __syncthreads();
+    for (int a = 0; a < 3; ++a) {
+        // thread t owns reversed keys [t*kPer, (t+1)*kPer): key = kBins - 1 - r
+        uint32_t local = 0;
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const uint32_t r = threadIdx.x * kPer + k;
+            if (r < kBins) local += ws.hist[a * kBins + (kBins - 1 - r)];
+        }
+        part[threadIdx.x] = local;
+        __syncthreads();
+        for (uint32_t off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele
+            const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const uint32_t total = part[kScanThreads - 1];
+        uint32_t run = seg_base + part[threadIdx.x] - local;
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const uint32_t r = threadIdx.x * kPer + k;
+            if (r < kBins) {
+                const uint32_t key = kBins - 1 - r;
+                ws.bin_start[a * kBins + key] = run;
+                run += ws.hist[a * kBins + key];
+            }
+        }
+        const uint32_t padded = (total + per_item - 1) / per_item * per_item;
+        for (uint32_t p = total + threadIdx.x; p < padded; p += kScanThreads) ws.sorted[seg_base + p] = kInvalid;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            PlanMeta *m = ws.meta;
+            m->count[a] = total;
+            m->seg_pos[a] = seg_base;
+            m->seg_item[a] = (a == 0 ? 0u : m->seg_item[a - 1] + (m->seg_pos[a] - m->seg_pos[a - 1]) / per_item);
+            seg_base += padded;
+            if (a == 2) {
+                m->seg_pos[3] = seg_base;
+                m->seg_item[3] = m->seg_item[2] + padded / per_item;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Scatter message indices to their sorted positions.  Each pass handles kThreads * kR
+// messages: local ranks come from LDS atomics, then one global atomic per non-empty key
+// reserves the workgroup's range.
+constexpr int kR = 8;
+__global__ __launch_bounds__(kThreads) void k_scatter(PlanWs ws)
+{
+    __shared__ uint32_t lc[3 * kLdsKeys];
+    const PlanDesc d = *ws.desc;
+    const uint64_t chunk = uint64_t(kThreads) * kR;
+    for (uint64_t base = uint64_t(blockIdx.x) * chunk; base < d.n; base += uint64_t(gridDim.x) * chunk) {
+        for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) lc[i] = 0;
+        __syncthreads();
+        uint32_t slot[kR], rank[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const uint64_t i = base + uint64_t(r) * kThreads + threadIdx.x;
+            slot[r] = kInvalid;
+            rank[r] = 0;
+            if (i < d.n) {
+                const int a = msg_algo(d, i);
+                if (a >= 0 && a < 3) {
+                    const uint32_t key = msg_key(d.lens[i], d.sort);
+                    slot[r] = uint32_t(a) * kBins + key;
+                    if (key < kLdsKeys) {
+                        const uint32_t ls = uint32_t(a) * kLdsKeys + key;
+                        const uint32_t first = __builtin_amdgcn_readfirstlane(ls);
+                        const uint64_t same = __ballot(ls == first);
+                        const uint64_t active = __ballot(1);
+                        if (same == active) {
+                            uint32_t b = 0;
+                            if ((active & lane_mask_lt()) == 0) b = atomicAdd(&lc[ls], uint32_t(__popcll(active)));
+                            b = __builtin_amdgcn_readfirstlane(b);
+                            rank[r] = b + uint32_t(__popcll(active & lane_mask_lt()));
+                        } else {
+                            rank[r] = atomicAdd(&lc[ls], 1u);
+                        }
+                    } else {
+                        rank[r] = ws.bin_start[slot[r]] + atomicAdd(&ws.cursor[slot[r]], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // reserve this pass's range of each LDS key; lc[] becomes the absolute base
+        for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) {
+            const uint32_t c = lc[i];
+            if (c) {
+                const uint32_t s = (i / kLdsKeys) * kBins + (i % kLdsKeys);
+                lc[i] = ws.bin_start[s] + atomicAdd(&ws.cursor[s], c);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            if (slot[r] == kInvalid) continue;
+            const uint64_t i = base + uint64_t(r) * kThreads + threadIdx.x;
+            const uint32_t a = slot[r] / kBins, key = slot[r] % kBins;
+            const uint32_t pos = key < kLdsKeys ? lc[a * kLdsKeys + key] + rank[r] : rank[r];
+            ws.sorted[pos] = uint32_t(i);
+        }
+        __syncthreads();
+    }
+}
+
+// Estimated cost of an item: the (capped) block-count key of its first message -- the
+// largest in the item -- times the algorithm's ops per block, times messages per lane.
+// Keys are non-increasing along a segment, so costs are too.
+__device__ __forceinline__ uint64_t item_cost(const PlanWs &ws, const PlanDesc &d, const PlanMeta &m, int a,
+                                              uint32_t k)
+{
+    const uint32_t per_item = 64u * uint32_t(d.mpl);
+    const uint32_t idx = ws.sorted[m.seg_pos[a] + k * per_item];
+    const uint64_t key = idx == kInvalid ? 0 : msg_key(d.lens[idx], d.sort);
+    return key * algo_cost(a) * uint64_t(d.mpl);
+}
+
+// Number of items of segment b that go before an item of cost c from segment a.
+__device__ __forceinline__ uint32_t count_before(const PlanWs &ws, const PlanDesc &d, const PlanMeta &m, int b,
+                                                 int a, uint64_t c)
+{
+    uint32_t lo = 0, hi = m.seg_item[b + 1] - m.seg_item[b];  // items of b, costs non-increasing
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        const uint64_t cb = item_cost(ws, d, m, b, mid);
+        const bool before = cb > c || (cb == c && b < a);
+        if (before) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Merge the three segments' items by cost, longest first: order[rank] = item id.
+__global__ __launch_bounds__(kThreads) void k_items(PlanWs ws)
+{
+    const PlanDesc d = *ws.desc;
+    const PlanMeta m = *ws.meta;
+    const uint32_t total = m.seg_item[3];
+    unsigned long long local_cost = 0;
+    for (uint32_t it = blockIdx.x * kThreads + threadIdx.x; it < total; it += gridDim.x * kThreads) {
+        int a = 0;
+        while (a < 2 && it >= m.seg_item[a + 1]) ++a;
+        const uint32_t k = it - m.seg_item[a];
+        const uint64_t c = item_cost(ws, d, m, a, k);
+        uint32_t rank = k;
+        for (int b = 0; b < 3; ++b)
+            if (b != a) rank += count_before(ws, d, m, b, a, c);
+        ws.order[rank] = it;
+        local_cost += c;
+    }
+    if (local_cost) atomicAdd(&ws.meta->total_cost, local_cost);
+}
+
+// Zero the 32-byte slots of messages whose algorithm id is unknown.
+__global__ __launch_bounds__(kThreads) void k_zero_invalid(PlanWs ws)
+{
+    const PlanDesc d = *ws.desc;
+    if (!d.algos) return;
+    const uint64_t step = uint64_t(gridDim.x) * kThreads;
+    for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < d.n; i += step) {
+        if (d.algos[i] > SM3) {
+            HB_GLOBAL uint32_t *o = reinterpret_cast<HB_GLOBAL uint32_t *>(reinterpret_cast<uintptr_t>(d.out + i * d.stride));
+            for (uint32_t q = 0; q < d.stride / 4u; ++q) o[q] = 0u;
+        }
+    }
+}
+
+template <int A>
+__device__ __forceinline__ void hash_lane(const PlanDesc &d, uint32_t idx)
+{
+    uint32_t s[8];
+    hash_message<A>(d.msgs + d.offs[idx], d.lens[idx], s);
+    store_digest<A>(d.out + uint64_t(idx) * d.stride, s, d.stride);
+}
+
+// Persistent fused kernel: each wave takes items from the queue until none are left.
+// An item is 64 * mpl sorted positions of one algorithm; lane l hashes positions
+// l, l + 64, ... of it.  Items whose cost exceeds the average per-wave share run at raised
+// wave priority so the longest chains keep their issue slots.
+__global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
+{
+    const PlanDesc d = *ws.desc;
+    const PlanMeta *mp = ws.meta;
+    const uint32_t total = mp->seg_item[3];
+    const uint32_t per_item = 64u * uint32_t(d.mpl);
+    const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
+    const uint64_t share = mp->total_cost / (waves ? waves : 1);
+    const uint32_t lane = __lane_id();
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(&ws.meta->queue, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= total) break;
+        const uint32_t item = ws.order[it];
+        if (item >= total) continue;  // never taken when the ranks form a permutation
+        int a = 0;
+        while (a < 2 && item >= mp->seg_item[a + 1]) ++a;
+        const uint32_t pos0 = mp->seg_pos[a] + (item - mp->seg_item[a]) * per_item;
+        const uint32_t first = ws.sorted[pos0];
+        const uint64_t cost = first == kInvalid ? 0 : uint64_t(msg_key(d.lens[first], d.sort)) * algo_cost(a) * d.mpl;
+        if (cost > share) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
+        for (int j = 0; j < d.mpl; ++j) {
+            const uint32_t idx = ws.sorted[pos0 + uint32_t(j) * 64u + lane];
+            if (idx == kInvalid) continue;
+            if (a == MD5) hash_lane<MD5>(d, idx);
+            else if (a == SHA1) hash_lane<SHA1>(d, idx);
+            else hash_lane<SM3>(d, idx);
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------
+
+struct TuneKey {
+    std::string arch;
+    int cus;
+    int algo_mask;
+    int len_bucket;
+    bool operator<(const TuneKey &o) const
+    {
+        if (arch != o.arch) return arch < o.arch;
+        if (cus != o.cus) return cus < o.cus;
+        if (algo_mask != o.algo_mask) return algo_mask < o.algo_mask;
+        return len_bucket < o.len_bucket;
+    }
+};
+
+struct TuneChoice {
+    int waves_per_cu;
+    int mpl;
+};
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneChoice> g_tune_cache;
+static bool g_tune_loaded = false;
+
+// Optional persistence: HB_TUNE_CACHE names a text file of lines
+// "arch cus algo_mask bucket waves_per_cu msgs_per_lane".
+static void load_tune_cache()
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("HB_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int cus, mask, bucket, w, m;
+    while (std::fscanf(f, "%63s %d %d %d %d %d", arch, &cus, &mask, &bucket, &w, &m) == 6)
+        if (w > 0 && w <= 64 && m > 0 && m <= kMaxMpl) g_tune_cache[TuneKey{arch, cus, mask, bucket}] = TuneChoice{w, m};
+    std::fclose(f);
+}
+
+static void save_tune_cache()
+{
+    const char *path = std::getenv("HB_TUNE_CACHE");
+    if (!path) return;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : g_tune_cache)
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.arch.c_str(), kv.first.cus, kv.first.algo_mask,
+                     kv.first.len_bucket, kv.second.waves_per_cu, kv.second.mpl);
+    std::fclose(f);
+}
+
+}  // namespace hb
+
+struct hb_plan {
+    hb::PlanWs ws{};
+    int flags = 0;
+    int device = 0;
+    int cus = 0;
+    std::string arch;
+    int waves_per_cu = 16;
+    int mpl = 1;
+    int variant = 0;
+    bool tuned = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_mpl = 0, graph_sort = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;  // hash-kernel timing
+    double kernel_ms_sum = 0.0;
+    int kernel_ms_count = 0;
+    void *alloc = nullptr;
+};
+
+namespace hb {
+
+static void drop_graph(hb_plan *p)
+{
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+static int grid_items(const hb_plan *p) { return p->cus * 4; }
+
+// Event pair bracketing the next hash launch (reused once collected).
+static std::pair<hipEvent_t, hipEvent_t> take_events(hb_plan *p)
+{
+    if (!p->ev_free.empty()) {
+        auto e = p->ev_free.back();
+        p->ev_free.pop_back();
+        return e;
+    }
+    std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+    if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) return {nullptr, nullptr};
+    return e;
+}
+
+// Fold the durations of finished timed launches into the running average.
+static void collect_timing(hb_plan *p, bool wait)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> keep;
+    for (auto &e : p->ev_pending) {
+        if (!wait && hipEventQuery(e.second) != hipSuccess) { keep.push_back(e); continue; }
+        float ms = 0.f;
+        if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+            p->kernel_ms_sum += ms;
+            p->kernel_ms_count += 1;
+        }
+        p->ev_free.push_back(e);
+    }
+    p->ev_pending.swap(keep);
+}
+
+// Enqueue the pipeline (after k_set_desc) on stream s.  With `timed`, HIP events on s
+// bracket the persistent hashing kernel.
+static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
+{
+    const PlanWs &ws = p->ws;
+    const int g = grid_items(p);
+    hipLaunchKernelGGL(k_zero, dim3(g), dim3(kThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_hist, dim3(g), dim3(kThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_items, dim3(g), dim3(kThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_zero_invalid, dim3(g), dim3(kThreads), 0, s, ws);
+    const int hash_blocks = (p->cus * p->waves_per_cu + 3) / 4;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (timed) ev = take_events(p);
+    if (ev.first) hipEventRecord(ev.first, s);
+    hipLaunchKernelGGL(k_hash_persistent, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+    if (ev.first) {
+        hipEventRecord(ev.second, s);
+        p->ev_pending.push_back(ev);
+        if (p->ev_pending.size() > 64) collect_timing(p, false);
+    }
+    return hipGetLastError();
+}
+
+static int launch_run(hb_plan *p, const PlanDesc &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, d, p->ws.desc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "hb_plan_run: parameter kernel");
+    const bool use_graph = (p->flags & HB_PLAN_GRAPH) != 0;
+    if (use_graph) {
+        if (p->exec && (p->graph_mpl != d.mpl || p->graph_sort != d.sort)) drop_graph(p);
+        if (!p->exec) {
+            e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_error(e, "hb_plan_run: begin capture");
+            hipError_t le = enqueue_pipeline(p, p->cap_stream, false);
+            e = hipStreamEndCapture(p->cap_stream, &p->graph);
+            if (le != hipSuccess) { drop_graph(p); return hip_error(le, "hb_plan_run: captured launch"); }
+            if (e != hipSuccess) { drop_graph(p); return hip_error(e, "hb_plan_run: end capture"); }
+            e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) { drop_graph(p); return hip_error(e, "hb_plan_run: instantiate"); }
+            p->graph_mpl = d.mpl;
+            p->graph_sort = d.sort;
+        }
+        e = hipGraphLaunch(p->exec, s);
+        if (e != hipSuccess) return hip_error(e, "hb_plan_run: graph launch");
+        return HB_OK;
+    }
+    e = enqueue_pipeline(p, s, true);
+    if (e != hipSuccess) return hip_error(e, "hb_plan_run: launch");
+    return HB_OK;
+}
+
+// Time each launch choice on this run's input and keep the fastest (cached per device,
+// algorithm mix and mean message length).
+static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask)
+{
+    TuneKey key{p->arch, p->cus, algo_mask, 0};
+    for (uint64_t m = d0.n; m > 1; m >>= 1) key.len_bucket++;  // bucket: log2 of the batch size
+    load_tune_cache();
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            p->waves_per_cu = it->second.waves_per_cu;
+            p->mpl = it->second.mpl;
+            return HB_OK;
+        }
+    }
+    const int flags_saved = p->flags;
+    p->flags &= ~HB_PLAN_GRAPH;
+    float best = 1e30f;
+    TuneChoice bestc{p->waves_per_cu, p->mpl};
+    const int wpcs[] = {8, 16, 32};
+    const int mpls[] = {1, 2};
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    for (int mpl : mpls) {
+        for (int w : wpcs) {
+            p->waves_per_cu = w;
+            PlanDesc d = d0;
+            d.mpl = mpl;
+            p->mpl = mpl;
+            float tot = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {
+                hipEventRecord(a, s);
+                int rc = launch_run(p, d, s);
+                hipEventRecord(b, s);
+                if (rc != HB_OK) { p->flags = flags_saved; hipEventDestroy(a); hipEventDestroy(b); return rc; }
+                hipEventSynchronize(b);
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, a, b);
+                if (rep) tot += ms;  // first repetition is a warm-up
+            }
+            if (tot < best) { best = tot; bestc = TuneChoice{w, mpl}; }
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    collect_timing(p, true);
+    p->kernel_ms_sum = 0.0;
+    p->kernel_ms_count = 0;
+    p->flags = flags_saved;
+    p->waves_per_cu = bestc.waves_per_cu;
+    p->mpl = bestc.mpl;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = bestc;
+    }
+    save_tune_cache();
+    return HB_OK;
+}
+
+}  // namespace hb
+
+using namespace hb;
+
+extern "C" {
+
+int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
+{
+    if (!plan) return set_error(HB_EINVAL, "hb_plan_create: null plan pointer");
+    *plan = nullptr;
+    if (max_n == 0 || max_n > (1ull << 31))
+        return set_error(HB_EINVAL, "hb_plan_create: max_n must be in [1, 2^31]");
+    hb_plan *p = new hb_plan();
+    p->flags = flags;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_error(e, "hb_plan_create: hipGetDevice"); }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, p->device);
+    if (e != hipSuccess) { delete p; return hip_error(e, "hb_plan_create: properties"); }
+    p->cus = prop.multiProcessorCount;
+    p->arch = prop.gcnArchName;
+    const uint64_t items_cap = max_n / 64 + 4;
+    const uint64_t sorted_cap = max_n + 3ull * 64 * kMaxMpl;
+    auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    const uint64_t sz_desc = up(sizeof(PlanDesc)), sz_meta = up(sizeof(PlanMeta));
+    const uint64_t sz_bins = up(3ull * kBins * 4);
+    const uint64_t sz_sorted = up(sorted_cap * 4), sz_order = up(items_cap * 4);
+    const uint64_t total = sz_desc + sz_meta + 3 * sz_bins + sz_sorted + sz_order;
+    e = hipMalloc(&p->alloc, total);
+    if (e != hipSuccess) { delete p; return set_error(HB_ENOMEM, "hb_plan_create: workspace allocation failed"); }
+    char *c = static_cast<char *>(p->alloc);
+    p->ws.desc = reinterpret_cast<PlanDesc *>(c); c += sz_desc;
+    p->ws.meta = reinterpret_cast<PlanMeta *>(c); c += sz_meta;
+    p->ws.hist = reinterpret_cast<uint32_t *>(c); c += sz_bins;
+    p->ws.cursor = reinterpret_cast<uint32_t *>(c); c += sz_bins;
+    p->ws.bin_start = reinterpret_cast<uint32_t *>(c); c += sz_bins;
+    p->ws.sorted = reinterpret_cast<uint32_t *>(c); c += sz_sorted;
+    p->ws.order = reinterpret_cast<uint32_t *>(c);
+    p->ws.max_n = max_n;
+    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        hb_plan_destroy(p);
+        return hip_error(e, "hb_plan_create: stream/event");
+    }
+    if (const char *w = std::getenv("HB_WAVES_PER_CU")) p->waves_per_cu = std::atoi(w) > 0 ? std::atoi(w) : 16;
+    *plan = p;
+    return HB_OK;
+}
+
+int hb_plan_run(hb_plan *p, const uint8_t *algos, int algo, const uint8_t *messages, const uint64_t *offsets,
+                const uint64_t *lengths, uint64_t n, uint8_t *digests_out, void *stream)
+{
+    if (!p) return set_error(HB_EINVAL, "hb_plan_run: null plan");
+    if (!algos && digest_size(algo) == 0) return set_error(HB_EINVAL, "hb_plan_run: unknown algorithm id");
+    if (n == 0) return HB_OK;
+    if (n > p->ws.max_n) return set_error(HB_EINVAL, "hb_plan_run: n exceeds the plan's max_n");
+    if (!messages || !offsets || !lengths || !digests_out)
+        return set_error(HB_EINVAL, "hb_plan_run: null device pointer");
+    if (reinterpret_cast<uintptr_t>(digests_out) & 3u)
+        return set_error(HB_EINVAL, "hb_plan_run: digests_out must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PlanDesc d{};
+    d.algos = algos;
+    d.msgs = messages;
+    d.offs = offsets;
+    d.lens = lengths;
+    d.out = digests_out;
+    d.n = n;
+    d.stride = algos ? 32u : uint32_t(digest_size(algo));
+    d.algo = algos ? 0 : algo;
+    d.sort = (p->flags & HB_PLAN_NO_SORT) ? 0 : 1;
+    if ((p->flags & HB_PLAN_AUTOTUNE) && !p->tuned) {
+        d.mpl = p->mpl;
+        const int mask = algos ? 7 : (1 << algo);
+        int rc = autotune(p, d, s, mask);
+        if (rc != HB_OK) return rc;
+        p->tuned = true;
+    }
+    d.mpl = p->mpl;
+    return launch_run(p, d, s);
+}
+
+int hb_plan_config(const hb_plan *p, int *waves_per_cu, int *msgs_per_lane, int *variant)
+{
+    if (!p) return set_error(HB_EINVAL, "hb_plan_config: null plan");
+    if (waves_per_cu) *waves_per_cu = p->waves_per_cu;
+    if (msgs_per_lane) *msgs_per_lane = p->mpl;
+    if (variant) *variant = p->variant;
+    return HB_OK;
+}
+
+int hb_plan_set_config(hb_plan *p, int waves_per_cu, int msgs_per_lane, int variant)
+{
+    if (!p) return set_error(HB_EINVAL, "hb_plan_set_config: null plan");
+    if (waves_per_cu < 0 || waves_per_cu > 64 || msgs_per_lane < 0 || msgs_per_lane > kMaxMpl || variant < 0)
+        return set_error(HB_EINVAL, "hb_plan_set_config: out of range");
+    if (waves_per_cu) p->waves_per_cu = waves_per_cu;
+    if (msgs_per_lane) p->mpl = msgs_per_lane;
+    p->variant = variant;
+    p->tuned = true;
+    drop_graph(p);
+    return HB_OK;
+}
+
+double hb_plan_kernel_ms(hb_plan *p)
+{
+    if (!p) return -1.0;
+    collect_timing(p, true);
+    if (p->kernel_ms_count == 0) return -1.0;
+    const double r = p->kernel_ms_sum / p->kernel_ms_count;
+    p->kernel_ms_sum = 0.0;
+    p->kernel_ms_count = 0;
+    return r;
+}
+
+void hb_plan_destroy(hb_plan *p)
+{
+    if (!p) return;
+    if (p->cap_stream) hipStreamSynchronize(p->cap_stream);
+    hipDeviceSynchronize();
+    drop_graph(p);
+    collect_timing(p, true);
+    for (auto &e : p->ev_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    if (p->alloc) hipFree(p->alloc);
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libhb (declared in include/hb.h).
+
+Argument marshalling only: every hashing step runs in the HIP library.  Device buffers are
+torch CUDA tensors (uint8 messages, int64 offsets/lengths holding byte counts < 2^63);
+the stream is torch's current stream unless one is given.  If libhb.so is missing the
+binding raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+
+from . import DIGEST_SIZE, MD5, SHA1, SM3
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "libhb.so"
+HEADER = PKG.parent / "include" / "hb.h"
+
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_EHIP, HB_EBUDGET, HB_EBUSY = 0, -1, -2, -3, -4, -5
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT = 1, 2, 4
+ALGO_IDS = {"md5": MD5, "sha1": SHA1, "sm3": SM3}
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_i = ctypes.c_int
+
+
+class HBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libhb status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhb.so (built by paper_2407_09333_amd.build); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2407_09333_amd.build.build() first")
+        L = ctypes.CDLL(str(LIB_PATH))
+        L.hb_digest_size.argtypes = [_i]
+        L.hb_digest_size.restype = ctypes.c_size_t
+        L.hb_last_error.restype = ctypes.c_char_p
+        L.hb_device_info.argtypes = [ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                     ctypes.c_char_p, ctypes.c_size_t]
+        L.hash_batch.argtypes = [_i, _vp, _vp, _vp, _u64, _vp, _vp]
+        L.hash_batch_strided.argtypes = [_i, _vp, _vp, _vp, _u64, _vp, _u64, _vp]
+        L.hash_batch_fixed.argtypes = [_i, _vp, _u64, _u64, _vp, _vp]
+        L.hash_batch_mixed.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, _vp]
+        if hasattr(L, "hb_plan_create"):
+            L.hb_plan_create.argtypes = [ctypes.POINTER(_vp), _u64, _i]
+            L.hb_plan_run.argtypes = [_vp, _vp, _i, _vp, _vp, _vp, _u64, _vp, _vp]
+            L.hb_plan_config.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
+            L.hb_plan_set_config.argtypes = [_vp, _i, _i, _i]
+            L.hb_plan_kernel_ms.argtypes = [_vp]
+            L.hb_plan_kernel_ms.restype = ctypes.c_double
+            L.hb_plan_destroy.argtypes = [_vp]
+            L.hb_plan_destroy.restype = None
+        if hasattr(L, "hash_batch_host"):
+            L.hash_batch_host.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _u64]
+        if hasattr(L, "hb_server_create"):
+            L.hb_server_create.argtypes = [ctypes.POINTER(_vp), _i, _u64, _i]
+            L.hb_server_submit.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _u64, _vp,
+                                           ctypes.POINTER(_u64)]
+            L.hb_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(_i)]
+            L.hb_server_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(_i)]
+            L.hb_server_times.argtypes = [_vp, _u64] + [ctypes.POINTER(ctypes.c_double)] * 4
+            L.hb_server_stats.argtypes = [_vp] + [ctypes.POINTER(_u64)] * 4
+            L.hb_server_now.argtypes = [_vp]
+            L.hb_server_now.restype = ctypes.c_double
+            L.hb_server_destroy.argtypes = [_vp]
+            L.hb_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/hb.h."""
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hb_\w+|hash_batch\w*)\s*\(", text)))
+
+
+def last_error() -> str:
+    return lib().hb_last_error().decode()
+
+
+def check(status: int) -> int:
+    if status != HB_OK:
+        raise HBError(status, last_error())
+    return status
+
+
+def algo_id(a) -> int:
+    return ALGO_IDS[a] if isinstance(a, str) else int(a)
+
+
+def digest_size(algo) -> int:
+    return int(lib().hb_digest_size(algo_id(algo)))
+
+
+def device_info() -> dict:
+    cu, ws, clk = _i(), _i(), _i()
+    name = ctypes.create_string_buffer(64)
+    check(lib().hb_device_info(ctypes.byref(cu), ctypes.byref(ws), ctypes.byref(clk), name, 64))
+    return {"cu_count": cu.value, "wave_size": ws.value, "clock_khz": clk.value,
+            "arch": name.value.decode()}
+
+
+# ---------------------------------------------------------------------------------------
+# torch marshalling helpers
+# ---------------------------------------------------------------------------------------
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr(stream) -> int | None:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_u8(x):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint8).reshape(-1))
+    if not x.is_cuda:
+        x = x.cuda()
+    assert x.dtype == torch.uint8 and x.is_contiguous()
+    return x
+
+
+def _dev_i64(x):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x).astype(np.int64, copy=False).reshape(-1))
+    if not x.is_cuda:
+        x = x.cuda()
+    assert x.dtype == torch.int64 and x.is_contiguous()
+    return x
+
+
+def _ptr(t) -> int | None:
+    return t.data_ptr() if t is not None else None
+
+
+def hash_batch(algo, messages, offsets, lengths, out=None, stride: int | None = None, stream=None):
+    """Plain batch hashing; returns an (n, stride) uint8 CUDA tensor of digests."""
+    torch = _torch()
+    a = algo_id(algo)
+    msgs, offs, lens = _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+    n = offs.numel()
+    ds = DIGEST_SIZE.get(a, 32)
+    stride = stride or ds
+    if out is None:
+        out = torch.empty((n, stride), dtype=torch.uint8, device=msgs.device)
+    check(lib().hash_batch_strided(a, _ptr(msgs), _ptr(offs), _ptr(lens), n, _ptr(out), stride,
+                                   _stream_ptr(stream)))
+    return out
+
+
+def hash_batch_fixed(algo, messages, n: int, msg_len: int, out=None, stream=None):
+    """n contiguous messages of msg_len bytes; returns (n, digest) uint8 CUDA tensor."""
+    torch = _torch()
+    a = algo_id(algo)
+    msgs = _dev_u8(messages)
+    assert msgs.numel() >= n * msg_len
+    if out is None:
+        out = torch.empty((n, DIGEST_SIZE.get(a, 32)), dtype=torch.uint8, device=msgs.device)
+    check(lib().hash_batch_fixed(a, _ptr(msgs), n, msg_len, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def hash_batch_mixed(algos, messages, offsets, lengths, out=None, stream=None):
+    """Per-message algorithm ids, plain form (one launch per algorithm); (n, 32) digests."""
+    torch = _torch()
+    al, msgs, offs, lens = _dev_u8(algos), _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+    n = offs.numel()
+    if out is None:
+        out = torch.empty((n, 32), dtype=torch.uint8, device=msgs.device)
+    check(lib().hash_batch_mixed(_ptr(al), _ptr(msgs), _ptr(offs), _ptr(lens), n, _ptr(out),
+                                 _stream_ptr(stream)))
+    return out
+
+
+class Plan:
+    """Batched form: bucketed, longest-first persistent launch captured in a hipGraph."""
+
+    def __init__(self, max_n: int, flags: int = PLAN_GRAPH):
+        self._h = _vp()
+        check(lib().hb_plan_create(ctypes.byref(self._h), max_n, flags))
+        self.max_n = max_n
+
+    def run(self, messages, offsets, lengths, algo=None, algos=None, out=None, stream=None):
+        torch = _torch()
+        msgs, offs, lens = _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+        n = offs.numel()
+        al = _dev_u8(algos) if algos is not None else None
+        a = algo_id(algo) if algo is not None else 0
+        stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
+        if out is None:
+            out = torch.empty((n, stride), dtype=torch.uint8, device=msgs.device)
+        check(lib().hb_plan_run(self._h, _ptr(al), a, _ptr(msgs), _ptr(offs), _ptr(lens), n,
+                                _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def config(self) -> dict:
+        w, m, v = _i(), _i(), _i()
+        check(lib().hb_plan_config(self._h, ctypes.byref(w), ctypes.byref(m), ctypes.byref(v)))
+        return {"waves_per_cu": w.value, "msgs_per_lane": m.value, "variant": v.value}
+
+    def set_config(self, waves_per_cu: int = 0, msgs_per_lane: int = 0, variant: int = 0):
+        check(lib().hb_plan_set_config(self._h, waves_per_cu, msgs_per_lane, variant))
+
+    def kernel_ms(self) -> float:
+        return float(lib().hb_plan_kernel_ms(self._h))
+
+    def close(self):
+        if self._h:
+            lib().hb_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hash_batch_host(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
+                    algos: np.ndarray | None = None, chunk_bytes: int = 64 << 20) -> np.ndarray:
+    """Host-resident inputs: chunked H2D copies overlapped with hashing; numpy digests."""
+    msgs = np.ascontiguousarray(messages, dtype=np.uint8).reshape(-1)
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    lens = np.ascontiguousarray(lengths, dtype=np.uint64)
+    n = offs.size
+    al = np.ascontiguousarray(algos, dtype=np.uint8) if algos is not None else None
+    a = algo_id(algo) if algo is not None else 0
+    stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
+    out = np.zeros((max(n, 1), stride), np.uint8)
+    check(lib().hash_batch_host(al.ctypes.data if al is not None else None, a,
+                                msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
+                                lens.ctypes.data, n, out.ctypes.data, chunk_bytes))
+    return out[:n]

@@ -1,0 +1,147 @@
+"""Parity of the plain HIP path (hash_batch / hash_batch_fixed / hash_batch_mixed) with
+the CPU oracle: every digest bit-exact on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_09333_amd import workloads
+from tests.gpu_util import assert_same, check_guard, guarded_out, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = [0, 1, 2]
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2407_09333_amd import hb as _hb
+
+    return _hb
+
+
+def test_md5_4096_by_55(hb):
+    b = workloads.cfg_md5_4096x55()
+    print("case md5 4096x55", flush=True)
+    got = hb.hash_batch_fixed(0, b.messages, b.n, 55).cpu().numpy()
+    want = oracle.hash_batch(0, b.messages, b.offsets, b.lengths)
+    assert_same(got, want, "md5 4096x55")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("L", [0, 1, 3, 4, 9, 55, 56, 63, 64, 65, 119, 120, 127, 128, 200, 1023, 1024, 1029])
+def test_fixed_lengths(hb, algo, L):
+    n = 300  # ragged: not a multiple of the 256-lane workgroup
+    b = workloads.fixed_batch(algo, n, L, seed=100 + L)
+    print(f"case fixed algo={algo} L={L}", flush=True)
+    msgs = b.messages if b.messages.size else np.zeros(1, np.uint8)
+    got = hb.hash_batch_fixed(algo, msgs, n, L).cpu().numpy()
+    assert_same(got, oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), f"fixed L={L}")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_every_length_0_to_300_packed(hb, algo):
+    lens = np.arange(301, dtype=np.uint64)
+    offs = workloads.packed(lens)
+    msgs = workloads.host_random_bytes(int(lens.sum()), seed=31)
+    print(f"case packed 0..300 algo={algo}", flush=True)
+    ds = oracle.DIGEST_SIZE[algo]
+    buf, out = guarded_out(lens.size, ds)
+    hb.hash_batch(algo, msgs, offs, lens, out=out)
+    check_guard(buf, lens.size, ds)
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, msgs, offs, lens), "packed 0..300")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_uneven_uniform_0_4096(hb, algo):
+    b = workloads.uniform_lengths_batch(algo, 5000, 4096, seed=3)
+    print(f"case uneven algo={algo}", flush=True)
+    got = hb.hash_batch(algo, b.messages, b.offsets, b.lengths).cpu().numpy()
+    assert_same(got, oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), "uneven")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_alignment_sweep_same_digest(hb, algo):
+    base = workloads.host_random_bytes(1200, seed=44)
+    msgs = np.concatenate([np.zeros(16, np.uint8), base, np.zeros(16, np.uint8)])
+    # the same 1000-byte message placed at offsets 0..15 of a larger buffer
+    buf = np.zeros(16 * 1100, np.uint8)
+    offs = np.zeros(16, np.uint64)
+    for r in range(16):
+        o = r * 1100 + r
+        buf[o:o + 1000] = base[:1000]
+        offs[r] = o
+    lens = np.full(16, 1000, np.uint64)
+    print(f"case alignment algo={algo}", flush=True)
+    got = hb.hash_batch(algo, buf, offs, lens).cpu().numpy()
+    want = oracle.hash_one(algo, base[:1000])
+    for r in range(16):
+        assert got[r].tobytes() == want, r
+    del msgs
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_overlapping_and_permuted_messages(hb, algo):
+    data = workloads.host_random_bytes(5000, seed=45)
+    rng = np.random.default_rng(7)
+    offs = rng.integers(0, 2500, size=777).astype(np.uint64)
+    lens = rng.integers(0, 2500, size=777).astype(np.uint64)
+    print(f"case overlap algo={algo}", flush=True)
+    got = hb.hash_batch(algo, data, offs, lens).cpu().numpy()
+    assert_same(got, oracle.hash_batch(algo, data, offs, lens), "overlap")
+    perm = rng.permutation(777)
+    got2 = hb.hash_batch(algo, data, offs[perm], lens[perm]).cpu().numpy()
+    assert_same(got2, got[perm], "permutation")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_strided_output_zero_fills(hb, algo):
+    b = workloads.uniform_lengths_batch(algo, 400, 300, seed=46)
+    print(f"case strided algo={algo}", flush=True)
+    buf, out = guarded_out(b.n, 36)
+    hb.hash_batch(algo, b.messages, b.offsets, b.lengths, out=out, stride=36)
+    check_guard(buf, b.n, 36)
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, b.messages, b.offsets, b.lengths, out_stride=36),
+                "strided")
+
+
+def test_mixed_plain(hb):
+    b = workloads.mixed_batch(400_000, seed=4, cap=1 << 15)
+    al = b.algos.copy()
+    al[::97] = 9  # unknown ids leave an all-zero slot
+    print(f"case mixed plain n={b.n}", flush=True)
+    got = hb.hash_batch_mixed(al, b.messages, b.offsets, b.lengths).cpu().numpy()
+    want = oracle.hash_batch(b.algos, b.messages, b.offsets, b.lengths)
+    want[::97] = 0
+    assert_same(got, want, "mixed plain")
+
+
+def test_n_zero_and_one(hb):
+    import torch
+
+    out = torch.full((1, 32), 7, dtype=torch.uint8, device="cuda")
+    msgs = workloads.host_random_bytes(100, seed=1)
+    hb.hash_batch(2, msgs, np.zeros(0, np.uint64), np.zeros(0, np.uint64), out=out[:0])
+    assert (out.cpu().numpy() == 7).all()
+    got = hb.hash_batch(2, msgs, np.array([5], np.uint64), np.array([90], np.uint64)).cpu().numpy()
+    assert got[0].tobytes() == oracle.hash_one(2, msgs[5:95])
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_full_size_fixed_1m_x_1024_sampled(hb, algo):
+    """2^20 messages of 1,024 bytes in the bench's launch configuration; 20,000 sampled
+    digests checked against the oracle one by one, the rest for internal consistency."""
+    import torch
+
+    b = workloads.cfg_fixed_1m_x_1024(algo, device="cuda")
+    print(f"case full fixed algo={algo}", flush=True)
+    got = hb.hash_batch_fixed(algo, b.messages, b.n, 1024)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(algo)
+    idx = np.unique(np.concatenate([rng.choice(b.n, 20000, replace=False), [0, 1, b.n - 2, b.n - 1]]))
+    host = b.messages.view(b.n, 1024)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    want = oracle.hash_batch(algo, host.reshape(-1), np.arange(idx.size, dtype=np.uint64) * 1024,
+                             np.full(idx.size, 1024, np.uint64))
+    assert_same(got[torch.from_numpy(idx).cuda()].cpu().numpy(), want, "full fixed sampled")
