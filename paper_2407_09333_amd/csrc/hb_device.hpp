@@ -272,6 +272,34 @@ __device__ __forceinline__ void load_full_block(const Msg &m, uint64_t blk, uint
     for (int i = 0; i < 16; ++i) w[i] = perm(raw[i + 1], raw[i], m.sel);
 }
 
+// Blocks blk and blk + 1, both wholly inside the message, from one burst of 33 dwords:
+// the two halves of each 128-byte L2 line are read together rather than one block apart,
+// so the line is not evicted and fetched again between them.  `aligned` (wave-uniform)
+// means every lane's message starts on a dword, so little-endian words need no realignment.
+template <bool BE>
+__device__ __forceinline__ void load_full_pair(const Msg &m, uint64_t blk, bool aligned, uint32_t w0[16],
+                                               uint32_t w1[16])
+{
+    const HB_GLOBAL uint32_t *q = m.p + blk * 16u;
+    uint32_t raw[33];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        u32x4 v = *reinterpret_cast<const HB_GLOBAL u32x4_a4 *>(q + 4 * k);
+        raw[4 * k + 0] = v.x; raw[4 * k + 1] = v.y; raw[4 * k + 2] = v.z; raw[4 * k + 3] = v.w;
+    }
+    if (!BE && aligned) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) { w0[i] = raw[i]; w1[i] = raw[16 + i]; }
+        return;
+    }
+    raw[32] = q[m.r ? 32 : 31];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        w0[i] = perm(raw[i + 1], raw[i], m.sel);
+        w1[i] = perm(raw[i + 17], raw[i + 16], m.sel);
+    }
+}
+
 // Any block of the padded message, including the tail block (message bytes, 0x80,
 // zeros), the length-only block and, when `last`, the 64-bit bit length in words 14-15
 // (low word first for MD5, high word first for SHA-1 / SM3).
@@ -316,7 +344,19 @@ __device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, 
     const uint64_t nb = (len + 8u) / 64u + 1u;
     const uint64_t nfast = len / 64u;
     init_state<A>(s);
-    for (uint64_t blk = 0; blk < nb; ++blk) {
+    uint64_t blk = 0;
+    if constexpr (A == MD5) {
+        // MD5 does the least work per byte, so it is the one HBM re-reads would bound:
+        // whole blocks go two at a time.
+        const bool aligned = __ballot(m.r != 0) == 0;
+        for (; blk + 2 <= nfast; blk += 2) {
+            uint32_t w0[16], w1[16];
+            load_full_pair<false>(m, blk, aligned, w0, w1);
+            compress<A>(s, w0);
+            compress<A>(s, w1);
+        }
+    }
+    for (; blk < nb; ++blk) {
         uint32_t w[16];
         if (blk < nfast) load_full_block(m, blk, w);
         else load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);

@@ -1,0 +1,228 @@
+// hb_host.cpp -- hashing messages that live in host memory.
+//
+// The batch is cut into chunks of about chunk_bytes of payload.  For each chunk the host
+// packs its messages (and rebased offsets, lengths, ids) into one of two pinned staging
+// buffers; the copy stream moves it to one of two device buffers; the compute stream waits
+// on the copy's event and runs the bucketed plan over the chunk; digests come back through
+// pinned memory on a third stream.  While chunk k is hashed, chunk k+1 is packed and
+// copied.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.hpp"
+
+namespace hb {
+
+namespace {
+
+struct Slot {
+    uint8_t *h_msgs = nullptr;       // pinned staging: payload | offsets | lengths | ids
+    uint64_t *h_offs = nullptr, *h_lens = nullptr;
+    uint8_t *h_ids = nullptr;
+    uint8_t *h_dig = nullptr;        // pinned digests
+    uint8_t *d_msgs = nullptr;
+    uint64_t *d_offs = nullptr, *d_lens = nullptr;
+    uint8_t *d_ids = nullptr, *d_dig = nullptr;
+    uint64_t cap_bytes = 0, cap_n = 0;
+    hipEvent_t copied = nullptr, hashed = nullptr, drained = nullptr;
+    // chunk bookkeeping for the drain step
+    uint64_t first = 0, count = 0;
+    bool busy = false;
+};
+
+struct HostPipe {
+    int device = -1;
+    hipStream_t copy = nullptr, compute = nullptr, back = nullptr;  // H2D, hashing, D2H
+    Slot slot[2];
+    hb_plan *plan = nullptr;
+    uint64_t plan_n = 0;
+
+    ~HostPipe()
+    {
+        if (compute) hipStreamSynchronize(compute);
+        if (copy) hipStreamSynchronize(copy);
+        if (back) hipStreamSynchronize(back);
+        for (Slot &s : slot) release(s);
+        if (plan) hb_plan_destroy(plan);
+        if (copy) hipStreamDestroy(copy);
+        if (compute) hipStreamDestroy(compute);
+        if (back) hipStreamDestroy(back);
+    }
+
+    static void release(Slot &s)
+    {
+        if (s.h_msgs) hipHostFree(s.h_msgs);
+        if (s.h_dig) hipHostFree(s.h_dig);
+        if (s.d_msgs) hipFree(s.d_msgs);
+        if (s.copied) hipEventDestroy(s.copied);
+        if (s.hashed) hipEventDestroy(s.hashed);
+        if (s.drained) hipEventDestroy(s.drained);
+        s = Slot{};
+    }
+};
+
+thread_local std::unique_ptr<HostPipe> t_pipe;
+
+uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Make sure slot s holds at least `bytes` of payload and `n` messages.
+int ensure_slot(Slot &s, uint64_t bytes, uint64_t n)
+{
+    if (s.cap_bytes >= bytes && s.cap_n >= n && s.h_msgs) return HB_OK;
+    HostPipe::release(s);
+    bytes = std::max<uint64_t>(up256(bytes), 1 << 20);
+    n = std::max<uint64_t>(n, 4096);
+    const uint64_t meta = up256(n * 8) * 2 + up256(n);
+    const uint64_t total = bytes + meta;
+    hipError_t e;
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s.h_msgs), total, hipHostMallocDefault)) != hipSuccess)
+        return set_error(HB_ENOMEM, "hash_batch_host: pinned staging allocation failed");
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s.h_dig), n * 32, hipHostMallocDefault)) != hipSuccess)
+        return set_error(HB_ENOMEM, "hash_batch_host: pinned digest allocation failed");
+    void *d = nullptr;
+    if ((e = hipMalloc(&d, total + n * 32)) != hipSuccess)
+        return set_error(HB_ENOMEM, "hash_batch_host: device staging allocation failed");
+    s.d_msgs = static_cast<uint8_t *>(d);
+    s.h_offs = reinterpret_cast<uint64_t *>(s.h_msgs + bytes);
+    s.h_lens = reinterpret_cast<uint64_t *>(s.h_msgs + bytes + up256(n * 8));
+    s.h_ids = s.h_msgs + bytes + 2 * up256(n * 8);
+    s.d_offs = reinterpret_cast<uint64_t *>(s.d_msgs + bytes);
+    s.d_lens = reinterpret_cast<uint64_t *>(s.d_msgs + bytes + up256(n * 8));
+    s.d_ids = s.d_msgs + bytes + 2 * up256(n * 8);
+    s.d_dig = s.d_msgs + total;
+    s.cap_bytes = bytes;
+    s.cap_n = n;
+    if ((e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s.hashed, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s.drained, hipEventDisableTiming)) != hipSuccess)
+        return hip_error(e, "hash_batch_host: events");
+    return HB_OK;
+}
+
+}  // namespace
+
+}  // namespace hb
+
+using namespace hb;
+
+extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                               const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                               uint8_t *digests_out_host, uint64_t chunk_bytes)
+{
+    if (!algos_host && digest_size(algo) == 0) return set_error(HB_EINVAL, "hash_batch_host: unknown algorithm id");
+    if (n == 0) return HB_OK;
+    if (!offsets_host || !lengths_host || !digests_out_host)
+        return set_error(HB_EINVAL, "hash_batch_host: null host pointer");
+    if (chunk_bytes == 0) chunk_bytes = 64ull << 20;
+    const uint64_t stride = algos_host ? 32 : uint64_t(digest_size(algo));
+    uint64_t any_bytes = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (lengths_host[i] >= (1ull << 61)) return set_error(HB_EINVAL, "hash_batch_host: length beyond 2^61");
+        any_bytes |= lengths_host[i];
+    }
+    if (any_bytes && !messages_host) return set_error(HB_EINVAL, "hash_batch_host: null messages");
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hash_batch_host: hipGetDevice");
+    if (!t_pipe || t_pipe->device != dev) {
+        t_pipe.reset(new HostPipe());
+        t_pipe->device = dev;
+        if ((e = hipStreamCreateWithFlags(&t_pipe->copy, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&t_pipe->compute, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&t_pipe->back, hipStreamNonBlocking)) != hipSuccess) {
+            t_pipe.reset();
+            return hip_error(e, "hash_batch_host: streams");
+        }
+    }
+    HostPipe &P = *t_pipe;
+    const uint64_t max_chunk_n = 1ull << 22;
+
+    // Chunk boundaries: greedy by payload bytes and message count.
+    std::vector<uint64_t> cuts{0};
+    uint64_t acc = 0, largest_chunk = 0, largest_n = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t L = lengths_host[i];
+        if (i > cuts.back() && (acc + L > chunk_bytes || i - cuts.back() >= max_chunk_n)) {
+            largest_chunk = std::max(largest_chunk, acc);
+            largest_n = std::max(largest_n, i - cuts.back());
+            cuts.push_back(i);
+            acc = 0;
+        }
+        acc += L;
+    }
+    largest_chunk = std::max(largest_chunk, acc);
+    largest_n = std::max(largest_n, n - cuts.back());
+    cuts.push_back(n);
+
+    if (!P.plan || P.plan_n < largest_n) {
+        if (P.plan) hb_plan_destroy(P.plan);
+        P.plan = nullptr;
+        int rc = hb_plan_create(&P.plan, std::max<uint64_t>(largest_n, 4096), HB_PLAN_GRAPH);
+        if (rc != HB_OK) return rc;
+        P.plan_n = std::max<uint64_t>(largest_n, 4096);
+    }
+    for (Slot &s : P.slot) {
+        int rc = ensure_slot(s, largest_chunk, largest_n);
+        if (rc != HB_OK) return rc;
+        s.busy = false;
+    }
+
+    auto drain = [&](Slot &s) -> int {
+        if (!s.busy) return HB_OK;
+        hipError_t de = hipEventSynchronize(s.drained);
+        if (de != hipSuccess) return hip_error(de, "hash_batch_host: chunk");
+        for (uint64_t k = 0; k < s.count; ++k)
+            std::memcpy(digests_out_host + (s.first + k) * stride, s.h_dig + k * stride, stride);
+        s.busy = false;
+        return HB_OK;
+    };
+
+    int rc = HB_OK;
+    const size_t nchunks = cuts.size() - 1;
+    for (size_t c = 0; c < nchunks && rc == HB_OK; ++c) {
+        Slot &s = P.slot[c & 1];
+        rc = drain(s);  // the slot's previous chunk must be finished before its buffers are reused
+        if (rc != HB_OK) break;
+        const uint64_t i0 = cuts[c], i1 = cuts[c + 1], cnt = i1 - i0;
+        uint64_t pos = 0;
+        for (uint64_t i = i0; i < i1; ++i) {
+            const uint64_t L = lengths_host[i];
+            if (L) std::memcpy(s.h_msgs + pos, messages_host + offsets_host[i], L);
+            s.h_offs[i - i0] = pos;
+            s.h_lens[i - i0] = L;
+            if (algos_host) s.h_ids[i - i0] = algos_host[i];
+            pos += L;
+        }
+        const uint64_t bytes = pos;
+        if (bytes) e = hipMemcpyAsync(s.d_msgs, s.h_msgs, bytes, hipMemcpyHostToDevice, P.copy);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_offs, s.h_offs, cnt * 8, hipMemcpyHostToDevice, P.copy);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_lens, s.h_lens, cnt * 8, hipMemcpyHostToDevice, P.copy);
+        if (e == hipSuccess && algos_host) e = hipMemcpyAsync(s.d_ids, s.h_ids, cnt, hipMemcpyHostToDevice, P.copy);
+        if (e == hipSuccess) e = hipEventRecord(s.copied, P.copy);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.compute, s.copied, 0);
+        if (e != hipSuccess) { rc = hip_error(e, "hash_batch_host: copy"); break; }
+        rc = hb_plan_run(P.plan, algos_host ? s.d_ids : nullptr, algo, s.d_msgs, s.d_offs, s.d_lens, cnt, s.d_dig,
+                         P.compute);
+        if (rc != HB_OK) break;
+        e = hipEventRecord(s.hashed, P.compute);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.back, s.hashed, 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.h_dig, s.d_dig, cnt * stride, hipMemcpyDeviceToHost, P.back);
+        if (e == hipSuccess) e = hipEventRecord(s.drained, P.back);
+        if (e != hipSuccess) { rc = hip_error(e, "hash_batch_host: digests"); break; }
+        s.first = i0;
+        s.count = cnt;
+        s.busy = true;
+    }
+    for (Slot &s : P.slot) {
+        int r2 = drain(s);
+        if (rc == HB_OK) rc = r2;
+    }
+    return rc;
+}

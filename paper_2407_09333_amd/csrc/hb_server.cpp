@@ -1,0 +1,550 @@
+// hb_server.cpp -- serving loop with continuous batching of hash requests.
+//
+// One background host thread owns the device side:
+//   admission   requests leave the FIFO in arrival order while their payload fits the
+//               device arena (the HBM budget) and a request slot is free;
+//   staging     each admitted request's messages are packed through a pinned ring and
+//               copied into its arena range on the copy stream (one event per request);
+//   steps       everything admitted and not yet launched forms the next device step,
+//               launched on the next free compute stream (each stream has its own plan),
+//               so a step can start while earlier ones are still hashing;
+//   completion  a finished step's digests come back through pinned memory, each request
+//               is marked done, and its arena range and slot are released.
+// A request that arrives while others run is admitted as soon as memory and a slot free
+// up, and its step overlaps the running ones on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_arena.hpp"
+#include "hb_internal.hpp"
+
+namespace hb {
+namespace {
+
+constexpr int kStreams = 3;                    // compute streams (steps in flight)
+constexpr uint64_t kMaxStepN = 1ull << 20;     // messages per device step
+constexpr uint64_t kRingBytes = 256ull << 20;  // pinned input staging ring
+constexpr uint64_t kPiece = 32ull << 20;       // staging copy granularity
+
+enum class St { Pending, Admitted, Launched, Done };
+
+struct Req {
+    uint64_t ticket = 0;
+    int algo = 0;                   // -1: per-message ids
+    const uint8_t *algos = nullptr;
+    const uint8_t *msgs = nullptr;
+    const uint64_t *offs = nullptr, *lens = nullptr;
+    uint64_t n = 0;
+    uint8_t *out = nullptr;
+    uint64_t payload = 0;           // sum of lengths
+    uint64_t arena_off = Arena::kFail;
+    St st = St::Pending;
+    int status = HB_OK;
+    double t_submit = 0, t_admit = 0, t_h2d = 0, t_done = 0;
+    hipEvent_t copied = nullptr;    // last staging copy of this request
+    bool stalled = false;           // was held back at the head of the queue
+};
+
+struct Step {
+    std::vector<Req *> reqs;
+    uint64_t n = 0;
+    bool mixed = false;
+    int algo = 0;
+    hipEvent_t done = nullptr;
+};
+
+struct RingPiece {
+    uint64_t start, end;
+    hipEvent_t ev;
+};
+
+}  // namespace
+}  // namespace hb
+
+using namespace hb;
+
+struct hb_server {
+    int device = 0;
+    uint64_t budget = 0;
+    int max_slots = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    std::thread thr;
+    std::deque<Req *> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
+    uint64_t next_ticket = 1;
+    int slots_used = 0;
+    // owned by the loop thread
+    std::vector<Req *> staged;      // admitted and copied in, waiting for a step
+    Arena arena;
+    uint8_t *d_arena = nullptr;
+    uint8_t *ring = nullptr;        // pinned
+    uint64_t ring_head = 0;
+    std::deque<RingPiece> ring_live;
+    std::vector<hipEvent_t> ev_pool;
+    hipStream_t copy_in = nullptr;
+    hipStream_t compute[kStreams] = {};
+    hb_plan *plan[kStreams] = {};
+    uint8_t *h_meta[kStreams] = {}; // pinned: offsets | lengths | ids | digests
+    uint8_t *d_meta[kStreams] = {};
+    std::unique_ptr<Step> busy[kStreams];
+    hipEvent_t ref = nullptr;
+    double ref_host = 0;
+    std::chrono::steady_clock::time_point t0;
+    // stats
+    std::atomic<uint64_t> completed{0}, steps{0}, stalls{0}, peak{0};
+    int fatal = HB_OK;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace hb {
+namespace {
+
+constexpr uint64_t meta_bytes(uint64_t n) { return n * (8 + 8 + 1 + 32) + 1024; }
+
+hipEvent_t take_event(hb_server *s)
+{
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+double event_host_time(hb_server *s, hipEvent_t e)
+{
+    float ms = 0.f;
+    if (e && hipEventElapsedTime(&ms, s->ref, e) == hipSuccess) return s->ref_host + double(ms) * 1e-3;
+    return s->now();
+}
+
+// Start offset of n free ring bytes (n <= kPiece).  Live pieces occupy one circular span
+// from the oldest piece's start to ring_head; the ring is never filled completely, so
+// ring_head == oldest start only when nothing is live.
+uint64_t ring_reserve(hb_server *s, uint64_t n)
+{
+    for (;;) {
+        while (!s->ring_live.empty() && hipEventQuery(s->ring_live.front().ev) == hipSuccess) {
+            s->ev_pool.push_back(s->ring_live.front().ev);
+            s->ring_live.pop_front();
+        }
+        uint64_t start = Arena::kFail;
+        if (s->ring_live.empty()) {
+            s->ring_head = 0;
+            start = 0;
+        } else {
+            const uint64_t fs = s->ring_live.front().start, h = s->ring_head;
+            if (h > fs) {                       // live span [fs, h)
+                if (h + n <= kRingBytes) start = h;
+                else if (n < fs) start = 0;
+            } else {                            // live span wraps: [fs, R) and [0, h)
+                if (h + n < fs) start = h;
+            }
+        }
+        if (start != Arena::kFail) {
+            s->ring_head = start + n;
+            return start;
+        }
+        hipEventSynchronize(s->ring_live.front().ev);
+    }
+}
+
+// Pack request r's messages into its arena range through the ring (messages laid back to
+// back in index order).  Records r->copied after the last piece.
+int stage_request(hb_server *s, Req *r)
+{
+    uint64_t dst = r->arena_off;
+    uint64_t i = 0, within = 0;  // message index and bytes of it already staged
+    while (i < r->n) {
+        // fill one piece
+        const uint64_t want = std::min<uint64_t>(kPiece, r->payload - (dst - r->arena_off));
+        if (want == 0) break;
+        const uint64_t at = ring_reserve(s, want);
+        uint64_t filled = 0;
+        while (filled < want && i < r->n) {
+            const uint64_t L = r->lens[i];
+            const uint64_t take = std::min<uint64_t>(L - within, want - filled);
+            if (take) std::memcpy(s->ring + at + filled, r->msgs + r->offs[i] + within, take);
+            filled += take;
+            within += take;
+            if (within == L) { ++i; within = 0; }
+        }
+        hipError_t e = hipMemcpyAsync(s->d_arena + dst, s->ring + at, filled, hipMemcpyHostToDevice, s->copy_in);
+        if (e != hipSuccess) return hip_error(e, "hb_server: staging copy");
+        hipEvent_t ev = take_event(s);
+        if (!ev || hipEventRecord(ev, s->copy_in) != hipSuccess) return set_error(HB_EHIP, "hb_server: staging event");
+        s->ring_live.push_back(RingPiece{at, at + filled, ev});
+        dst += filled;
+        // skip empty messages between pieces
+        while (i < r->n && r->lens[i] == 0) ++i;
+    }
+    r->copied = take_event(s);
+    if (!r->copied || hipEventRecord(r->copied, s->copy_in) != hipSuccess)
+        return set_error(HB_EHIP, "hb_server: copy event");
+    return HB_OK;
+}
+
+// Launch everything staged as one step on compute stream k.
+int launch_step(hb_server *s, int k)
+{
+    auto st = std::make_unique<Step>();
+    uint64_t n = 0;
+    size_t take = 0;
+    while (take < s->staged.size() && n + s->staged[take]->n <= kMaxStepN) n += s->staged[take++]->n;
+    if (take == 0) return HB_OK;
+    st->reqs.assign(s->staged.begin(), s->staged.begin() + take);
+    s->staged.erase(s->staged.begin(), s->staged.begin() + take);
+    st->n = n;
+    st->algo = st->reqs[0]->algo;
+    for (Req *r : st->reqs) st->mixed |= (r->algo < 0 || r->algo != st->algo);
+    const uint64_t stride = st->mixed ? 32 : uint64_t(digest_size(st->algo));
+    // step metadata: absolute arena offsets, lengths, per-message ids
+    uint64_t *ho = reinterpret_cast<uint64_t *>(s->h_meta[k]);
+    uint64_t *hl = ho + kMaxStepN;
+    uint8_t *hi = reinterpret_cast<uint8_t *>(hl + kMaxStepN);
+    uint64_t m = 0;
+    for (Req *r : st->reqs) {
+        uint64_t pos = r->arena_off;
+        for (uint64_t i = 0; i < r->n; ++i, ++m) {
+            ho[m] = pos;
+            hl[m] = r->lens[i];
+            hi[m] = uint8_t(r->algo < 0 ? r->algos[i] : r->algo);
+            pos += r->lens[i];
+        }
+        hipStreamWaitEvent(s->compute[k], r->copied, 0);
+        r->st = St::Launched;
+    }
+    uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
+    uint64_t *dl = dof + kMaxStepN;
+    uint8_t *di = reinterpret_cast<uint8_t *>(dl + kMaxStepN);
+    uint8_t *dd = di + kMaxStepN;
+    uint8_t *hd = hi + kMaxStepN;
+    hipStream_t cs = s->compute[k];
+    // on failure the step is parked on stream k with no event; the loop fails its requests
+    auto fail = [&](int rc) {
+        s->busy[k] = std::move(st);
+        return rc;
+    };
+    hipError_t e = hipMemcpyAsync(dof, ho, n * 8, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dl, hl, n * 8, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess && st->mixed) e = hipMemcpyAsync(di, hi, n, hipMemcpyHostToDevice, cs);
+    if (e != hipSuccess) return fail(hip_error(e, "hb_server: step metadata"));
+    int rc = hb_plan_run(s->plan[k], st->mixed ? di : nullptr, st->algo, s->d_arena, dof, dl, n, dd, cs);
+    if (rc != HB_OK) return fail(rc);
+    e = hipMemcpyAsync(hd, dd, n * stride, hipMemcpyDeviceToHost, cs);
+    if (e != hipSuccess) return fail(hip_error(e, "hb_server: digest copy"));
+    hipEvent_t done = take_event(s);
+    if (!done || hipEventRecord(done, cs) != hipSuccess) {
+        if (done) s->ev_pool.push_back(done);
+        return fail(set_error(HB_EHIP, "hb_server: step event"));
+    }
+    st->done = done;
+    s->busy[k] = std::move(st);
+    s->steps++;
+    return HB_OK;
+}
+
+// Finish the step on stream k: digests to the callers' buffers, release memory and slots.
+void finish_step(hb_server *s, int k, int status)
+{
+    Step *st = s->busy[k].get();
+    const uint64_t stride = st->mixed ? 32 : uint64_t(digest_size(st->algo));
+    const uint8_t *hd = s->h_meta[k] + kMaxStepN * 17;
+    const double t = s->now();
+    uint64_t m = 0;
+    for (Req *r : st->reqs) {
+        const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
+        if (status == HB_OK) {
+            if (ds == stride) std::memcpy(r->out, hd + m * stride, r->n * stride);
+            else
+                for (uint64_t i = 0; i < r->n; ++i) std::memcpy(r->out + i * ds, hd + (m + i) * stride, ds);
+        }
+        m += r->n;
+        if (r->copied) {
+            r->t_h2d = status == HB_OK ? event_host_time(s, r->copied) : t;
+            s->ev_pool.push_back(r->copied);
+            r->copied = nullptr;
+        }
+        if (r->payload) s->arena.release(r->arena_off, r->payload);
+    }
+    if (st->done) s->ev_pool.push_back(st->done);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (Req *r : st->reqs) {
+            r->t_done = t;
+            r->status = status;
+            r->st = St::Done;
+            s->slots_used--;
+        }
+    }
+    s->completed += st->reqs.size();
+    s->busy[k].reset();
+    s->cv_done.notify_all();
+}
+
+void loop(hb_server *s)
+{
+    hipSetDevice(s->device);
+    int next_stream = 0;
+    for (;;) {
+        // 1. admission, in arrival order
+        std::vector<Req *> newly;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            bool any_busy = false;
+            for (auto &b : s->busy) any_busy |= bool(b);
+            if (s->pending.empty() && s->staged.empty() && !any_busy) {
+                if (s->stop) break;
+                s->cv_work.wait_for(g, std::chrono::milliseconds(50));
+                continue;
+            }
+            while (!s->pending.empty() && s->slots_used < s->max_slots) {
+                Req *r = s->pending.front();
+                uint64_t off = 0;
+                if (r->payload) {
+                    off = s->arena.alloc(r->payload);
+                    if (off == Arena::kFail) break;
+                }
+                r->arena_off = off;
+                r->st = St::Admitted;
+                r->t_admit = s->now();
+                s->slots_used++;
+                s->pending.pop_front();
+                newly.push_back(r);
+            }
+            if (!s->pending.empty() && !s->pending.front()->stalled) {
+                s->pending.front()->stalled = true;
+                s->stalls++;
+            }
+            if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
+        }
+        // 2. staging copies
+        for (Req *r : newly) {
+            int rc = stage_request(s, r);
+            if (rc != HB_OK) { s->fatal = rc; }
+            s->staged.push_back(r);
+        }
+        // 3. launch a step on a free compute stream
+        if (!s->staged.empty()) {
+            for (int t = 0; t < kStreams; ++t) {
+                const int k = (next_stream + t) % kStreams;
+                if (!s->busy[k]) {
+                    int rc = launch_step(s, k);
+                    if (rc != HB_OK) {
+                        s->fatal = rc;
+                        if (s->busy[k]) {
+                            if (hipStreamSynchronize(s->compute[k]) != hipSuccess) rc = HB_EHIP;
+                            finish_step(s, k, rc);
+                        }
+                    }
+                    next_stream = (k + 1) % kStreams;
+                    break;
+                }
+            }
+        }
+        // 4. completions
+        bool progressed = false;
+        for (int k = 0; k < kStreams; ++k) {
+            if (!s->busy[k]) continue;
+            hipError_t q = hipEventQuery(s->busy[k]->done);
+            if (q == hipSuccess) { finish_step(s, k, HB_OK); progressed = true; }
+            else if (q != hipErrorNotReady) { finish_step(s, k, HB_EHIP); progressed = true; }
+        }
+        if (!progressed && newly.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+}  // namespace hb
+
+extern "C" {
+
+int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int max_slots)
+{
+    if (!out) return set_error(HB_EINVAL, "hb_server_create: null server pointer");
+    *out = nullptr;
+    if (hbm_budget_bytes < Arena::kAlign || max_slots <= 0)
+        return set_error(HB_EINVAL, "hb_server_create: budget must be >= 256 bytes and max_slots > 0");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_error(e, "hb_server_create: hipSetDevice");
+    auto s = std::make_unique<hb_server>();
+    s->device = device;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->t0 = std::chrono::steady_clock::now();
+    s->arena.reset(hbm_budget_bytes);
+    auto fail = [&](int rc, const char *what, hipError_t he) {
+        // partial resources are released by the destructor path below
+        hb_server *p = s.release();
+        p->stop = true;
+        hb_server_destroy(p);
+        return he != hipSuccess ? hip_error(he, what) : set_error(rc, what);
+    };
+    if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_arena), s->arena.capacity())) != hipSuccess)
+        return fail(HB_ENOMEM, "hb_server_create: device arena", hipSuccess);
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->ring), kRingBytes, hipHostMallocDefault)) != hipSuccess)
+        return fail(HB_ENOMEM, "hb_server_create: pinned ring", hipSuccess);
+    if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
+        return fail(HB_EHIP, "hb_server_create: stream", e);
+    for (int k = 0; k < kStreams; ++k) {
+        if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: stream", e);
+        int rc = hb_plan_create(&s->plan[k], kMaxStepN, 0);
+        if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN), hipHostMallocDefault)) !=
+            hipSuccess)
+            return fail(HB_ENOMEM, "hb_server_create: pinned step buffers", hipSuccess);
+        if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_meta[k]), meta_bytes(kMaxStepN))) != hipSuccess)
+            return fail(HB_ENOMEM, "hb_server_create: device step buffers", hipSuccess);
+    }
+    if ((e = hipEventCreate(&s->ref)) != hipSuccess) return fail(HB_EHIP, "hb_server_create: event", e);
+    if ((e = hipEventRecord(s->ref, s->copy_in)) != hipSuccess || (e = hipEventSynchronize(s->ref)) != hipSuccess)
+        return fail(HB_EHIP, "hb_server_create: reference event", e);
+    s->ref_host = s->now();
+    hb_server *p = s.release();
+    p->thr = std::thread(loop, p);
+    *out = p;
+    return HB_OK;
+}
+
+int hb_server_submit(hb_server *s, int algo_or_mixed, const uint8_t *algos, const uint8_t *messages,
+                     const uint64_t *offsets, const uint64_t *lengths, uint64_t n, uint8_t *digests_out,
+                     uint64_t *ticket)
+{
+    if (!s || !ticket) return set_error(HB_EINVAL, "hb_server_submit: null server or ticket pointer");
+    const bool mixed = algo_or_mixed == -1;
+    if (!mixed && digest_size(algo_or_mixed) == 0) return set_error(HB_EINVAL, "hb_server_submit: unknown algorithm id");
+    if (n == 0) return set_error(HB_EINVAL, "hb_server_submit: empty request");
+    if (n > kMaxStepN) return set_error(HB_EINVAL, "hb_server_submit: more than 2^20 messages in one request");
+    if (!offsets || !lengths || !digests_out || (mixed && !algos))
+        return set_error(HB_EINVAL, "hb_server_submit: null host pointer");
+    uint64_t payload = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (lengths[i] >= (1ull << 61)) return set_error(HB_EINVAL, "hb_server_submit: length beyond 2^61");
+        if (mixed && algos[i] > HB_SM3) return set_error(HB_EINVAL, "hb_server_submit: unknown algorithm id in algos");
+        payload += lengths[i];
+    }
+    if (payload && !messages) return set_error(HB_EINVAL, "hb_server_submit: null messages");
+    if (Arena::round_up(payload) > s->arena.capacity())
+        return set_error(HB_EBUDGET, "hb_server_submit: request payload exceeds the device budget");
+    auto r = std::make_unique<Req>();
+    r->algo = mixed ? -1 : algo_or_mixed;
+    r->algos = algos;
+    r->msgs = messages;
+    r->offs = offsets;
+    r->lens = lengths;
+    r->n = n;
+    r->out = digests_out;
+    r->payload = payload;
+    r->t_submit = s->now();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) return set_error(HB_EINVAL, "hb_server_submit: server is stopping");
+        r->ticket = s->next_ticket++;
+        *ticket = r->ticket;
+        s->pending.push_back(r.get());
+        s->all[r->ticket] = std::move(r);
+    }
+    s->cv_work.notify_one();
+    return HB_OK;
+}
+
+int hb_server_poll(hb_server *s, uint64_t ticket, int *done, int *status)
+{
+    if (!s || !done) return set_error(HB_EINVAL, "hb_server_poll: null pointer");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_poll: unknown ticket");
+    *done = it->second->st == St::Done;
+    if (status) *status = it->second->status;
+    return HB_OK;
+}
+
+int hb_server_wait(hb_server *s, uint64_t ticket, int64_t timeout_ms, int *status)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_wait: null server");
+    std::unique_lock<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_wait: unknown ticket");
+    Req *r = it->second.get();
+    auto ready = [&] { return r->st == St::Done; };
+    if (timeout_ms < 0) s->cv_done.wait(g, ready);
+    else if (!s->cv_done.wait_for(g, std::chrono::milliseconds(timeout_ms), ready))
+        return set_error(HB_EBUSY, "hb_server_wait: timed out");
+    if (status) *status = r->status;
+    return HB_OK;
+}
+
+int hb_server_times(hb_server *s, uint64_t ticket, double *t_submit, double *t_admit, double *t_h2d_done,
+                    double *t_done)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_times: null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_times: unknown ticket");
+    Req *r = it->second.get();
+    if (t_submit) *t_submit = r->t_submit;
+    if (t_admit) *t_admit = r->t_admit;
+    if (t_h2d_done) *t_h2d_done = r->t_h2d;
+    if (t_done) *t_done = r->t_done;
+    return HB_OK;
+}
+
+int hb_server_stats(hb_server *s, uint64_t *completed, uint64_t *nsteps, uint64_t *stalls, uint64_t *peak_bytes)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_stats: null server");
+    if (completed) *completed = s->completed;
+    if (nsteps) *nsteps = s->steps;
+    if (stalls) *stalls = s->stalls;
+    if (peak_bytes) *peak_bytes = s->peak;
+    return HB_OK;
+}
+
+double hb_server_now(hb_server *s) { return s ? s->now() : 0.0; }
+
+void hb_server_destroy(hb_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->thr.joinable()) s->thr.join();
+    for (int k = 0; k < kStreams; ++k) {
+        if (s->compute[k]) hipStreamSynchronize(s->compute[k]);
+        if (s->plan[k]) hb_plan_destroy(s->plan[k]);
+        if (s->h_meta[k]) hipHostFree(s->h_meta[k]);
+        if (s->d_meta[k]) hipFree(s->d_meta[k]);
+        if (s->compute[k]) hipStreamDestroy(s->compute[k]);
+    }
+    if (s->copy_in) {
+        hipStreamSynchronize(s->copy_in);
+        hipStreamDestroy(s->copy_in);
+    }
+    for (auto &p : s->ring_live) hipEventDestroy(p.ev);
+    for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
+    if (s->ref) hipEventDestroy(s->ref);
+    if (s->ring) hipHostFree(s->ring);
+    if (s->d_arena) hipFree(s->d_arena);
+    delete s;
+}
+
+}  // extern "C"

@@ -252,3 +252,66 @@ def hash_batch_host(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarr
                                 msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
                                 lens.ctypes.data, n, out.ctypes.data, chunk_bytes))
     return out[:n]
+
+
+class Server:
+    """Continuous-batching serving loop (hb_server_*).  Requests are host numpy buffers,
+    kept alive here until they complete."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, device: int = 0):
+        self._h = _vp()
+        check(lib().hb_server_create(ctypes.byref(self._h), device, hbm_budget_bytes, max_slots))
+        self._live = {}
+
+    def submit(self, messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
+               algos: np.ndarray | None = None) -> int:
+        msgs = np.ascontiguousarray(messages, dtype=np.uint8).reshape(-1)
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        lens = np.ascontiguousarray(lengths, dtype=np.uint64)
+        al = np.ascontiguousarray(algos, dtype=np.uint8) if algos is not None else None
+        a = -1 if al is not None else algo_id(algo)
+        stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
+        out = np.zeros((max(offs.size, 1), stride), np.uint8)
+        t = _u64()
+        check(lib().hb_server_submit(self._h, a, al.ctypes.data if al is not None else None,
+                                     msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
+                                     lens.ctypes.data, offs.size, out.ctypes.data, ctypes.byref(t)))
+        self._live[t.value] = (msgs, offs, lens, al, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        d, st = _i(), _i()
+        check(lib().hb_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(st)))
+        return bool(d.value), st.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> np.ndarray:
+        st = _i()
+        check(lib().hb_server_wait(self._h, ticket, timeout_ms, ctypes.byref(st)))
+        check(st.value)
+        msgs, offs, lens, al, out = self._live.pop(ticket)
+        return out[: offs.size]
+
+    def times(self, ticket: int) -> dict:
+        v = [ctypes.c_double() for _ in range(4)]
+        check(lib().hb_server_times(self._h, ticket, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("submit", "admit", "h2d_done", "done"), (x.value for x in v)))
+
+    def stats(self) -> dict:
+        v = [_u64() for _ in range(4)]
+        check(lib().hb_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("completed", "steps", "stalls", "peak_bytes"), (x.value for x in v)))
+
+    def now(self) -> float:
+        return float(lib().hb_server_now(self._h))
+
+    def close(self):
+        if self._h:
+            lib().hb_server_destroy(self._h)
+            self._h = _vp()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

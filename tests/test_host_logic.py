@@ -1,0 +1,24 @@
+"""Host-side logic that needs no GPU: the serving arena allocator, built with g++ (and
+with the address and undefined-behaviour sanitizers when available)."""
+import shutil
+import subprocess
+from pathlib import Path
+
+import pytest
+
+HERE = Path(__file__).resolve().parent
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_arena_allocator(tmp_path, sanitize):
+    exe = tmp_path / "arena_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", str(HERE / "cpp" / "arena_check.cpp"), "-o", str(exe)]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "arena ok" in out.stdout
