@@ -3,8 +3,9 @@
 // One background host thread owns the device side:
 //   admission   requests leave the FIFO in arrival order while their payload fits the
 //               device arena (the HBM budget) and a request slot is free;
-//   staging     each admitted request's messages are packed through a pinned ring and
-//               copied into its arena range on the copy stream (one event per request);
+//   staging     a pool of staging threads packs each admitted request's messages into
+//               pinned double buffers and copies them into its arena range, each thread
+//               on its own copy stream (one completion event per request);
 //   steps       everything admitted and not yet launched forms the next device step,
 //               launched on the next free compute stream (each stream has its own plan),
 //               so a step can start while earlier ones are still hashing;
@@ -36,8 +37,8 @@ namespace {
 
 constexpr int kStreams = 3;                    // compute streams (steps in flight)
 constexpr uint64_t kMaxStepN = 1ull << 20;     // messages per device step
-constexpr uint64_t kRingBytes = 256ull << 20;  // pinned input staging ring
-constexpr uint64_t kPiece = 32ull << 20;       // staging copy granularity
+constexpr int kStagers = 4;                    // staging threads
+constexpr uint64_t kPiece = 16ull << 20;       // staging copy granularity (per buffer half)
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -66,9 +67,13 @@ struct Step {
     hipEvent_t done = nullptr;
 };
 
-struct RingPiece {
-    uint64_t start, end;
-    hipEvent_t ev;
+// A staging thread's pinned double buffer and copy stream.
+struct Stager {
+    std::thread thr;
+    hipStream_t stream = nullptr;
+    uint8_t *buf = nullptr;          // 2 * kPiece pinned bytes
+    hipEvent_t half_free[2] = {nullptr, nullptr};
+    bool half_used[2] = {false, false};
 };
 
 }  // namespace
@@ -88,15 +93,17 @@ struct hb_server {
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
     uint64_t next_ticket = 1;
     int slots_used = 0;
+    std::deque<Req *> to_stage;     // admitted, waiting for a staging thread (under mu)
+    std::vector<Req *> staged;      // copies enqueued, waiting for a step (under mu)
+    std::condition_variable cv_stage;
+    Stager stager[kStagers];
+    bool stop_stagers = false;
+    int staging_inflight = 0;       // requests a staging thread is working on (under mu)
     // owned by the loop thread
-    std::vector<Req *> staged;      // admitted and copied in, waiting for a step
     Arena arena;
     uint8_t *d_arena = nullptr;
-    uint8_t *ring = nullptr;        // pinned
-    uint64_t ring_head = 0;
-    std::deque<RingPiece> ring_live;
     std::vector<hipEvent_t> ev_pool;
-    hipStream_t copy_in = nullptr;
+    hipStream_t copy_in = nullptr;  // reference-event stream
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams] = {};
     uint8_t *h_meta[kStreams] = {}; // pinned: offsets | lengths | ids | digests
@@ -135,70 +142,68 @@ double event_host_time(hb_server *s, hipEvent_t e)
     return s->now();
 }
 
-// Start offset of n free ring bytes (n <= kPiece).  Live pieces occupy one circular span
-// from the oldest piece's start to ring_head; the ring is never filled completely, so
-// ring_head == oldest start only when nothing is live.
-uint64_t ring_reserve(hb_server *s, uint64_t n)
+// Pack request r's messages (back to back, index order) into its arena range through
+// stager g's pinned double buffer, copying each filled half on g's stream.  Records
+// r->copied on that stream after the last piece.
+int stage_one(hb_server *s, Stager &g, int &half, Req *r)
 {
-    for (;;) {
-        while (!s->ring_live.empty() && hipEventQuery(s->ring_live.front().ev) == hipSuccess) {
-            s->ev_pool.push_back(s->ring_live.front().ev);
-            s->ring_live.pop_front();
+    uint64_t dst = r->arena_off, i = 0, within = 0;  // message index and bytes of it staged
+    const uint64_t end = r->arena_off + r->payload;
+    while (dst < end) {
+        const int h = half;
+        half ^= 1;
+        if (g.half_used[h]) {
+            hipError_t we = hipEventSynchronize(g.half_free[h]);
+            if (we != hipSuccess) return hip_error(we, "hb_server: staging wait");
         }
-        uint64_t start = Arena::kFail;
-        if (s->ring_live.empty()) {
-            s->ring_head = 0;
-            start = 0;
-        } else {
-            const uint64_t fs = s->ring_live.front().start, h = s->ring_head;
-            if (h > fs) {                       // live span [fs, h)
-                if (h + n <= kRingBytes) start = h;
-                else if (n < fs) start = 0;
-            } else {                            // live span wraps: [fs, R) and [0, h)
-                if (h + n < fs) start = h;
-            }
-        }
-        if (start != Arena::kFail) {
-            s->ring_head = start + n;
-            return start;
-        }
-        hipEventSynchronize(s->ring_live.front().ev);
-    }
-}
-
-// Pack request r's messages into its arena range through the ring (messages laid back to
-// back in index order).  Records r->copied after the last piece.
-int stage_request(hb_server *s, Req *r)
-{
-    uint64_t dst = r->arena_off;
-    uint64_t i = 0, within = 0;  // message index and bytes of it already staged
-    while (i < r->n) {
-        // fill one piece
-        const uint64_t want = std::min<uint64_t>(kPiece, r->payload - (dst - r->arena_off));
-        if (want == 0) break;
-        const uint64_t at = ring_reserve(s, want);
+        uint8_t *buf = g.buf + uint64_t(h) * kPiece;
+        const uint64_t want = std::min<uint64_t>(kPiece, end - dst);
         uint64_t filled = 0;
         while (filled < want && i < r->n) {
             const uint64_t L = r->lens[i];
             const uint64_t take = std::min<uint64_t>(L - within, want - filled);
-            if (take) std::memcpy(s->ring + at + filled, r->msgs + r->offs[i] + within, take);
+            if (take) std::memcpy(buf + filled, r->msgs + r->offs[i] + within, take);
             filled += take;
             within += take;
             if (within == L) { ++i; within = 0; }
         }
-        hipError_t e = hipMemcpyAsync(s->d_arena + dst, s->ring + at, filled, hipMemcpyHostToDevice, s->copy_in);
+        hipError_t e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, g.stream);
+        if (e == hipSuccess) e = hipEventRecord(g.half_free[h], g.stream);
         if (e != hipSuccess) return hip_error(e, "hb_server: staging copy");
-        hipEvent_t ev = take_event(s);
-        if (!ev || hipEventRecord(ev, s->copy_in) != hipSuccess) return set_error(HB_EHIP, "hb_server: staging event");
-        s->ring_live.push_back(RingPiece{at, at + filled, ev});
+        g.half_used[h] = true;
         dst += filled;
-        // skip empty messages between pieces
-        while (i < r->n && r->lens[i] == 0) ++i;
     }
-    r->copied = take_event(s);
-    if (!r->copied || hipEventRecord(r->copied, s->copy_in) != hipSuccess)
-        return set_error(HB_EHIP, "hb_server: copy event");
+    hipError_t e = hipEventCreate(&r->copied);
+    if (e == hipSuccess) e = hipEventRecord(r->copied, g.stream);
+    if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
     return HB_OK;
+}
+
+// Staging thread: take admitted requests in order, stage them, hand them to the loop.
+void stager_loop(hb_server *s, int w)
+{
+    hipSetDevice(s->device);
+    Stager &g = s->stager[w];
+    int half = 0;
+    for (;;) {
+        Req *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_stage.wait(lk, [&] { return s->stop_stagers || !s->to_stage.empty(); });
+            if (s->to_stage.empty()) return;
+            r = s->to_stage.front();
+            s->to_stage.pop_front();
+            s->staging_inflight++;
+        }
+        const int rc = stage_one(s, g, half, r);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (rc != HB_OK) r->status = rc;
+            s->staged.push_back(r);
+            s->staging_inflight--;
+        }
+        s->cv_work.notify_one();
+    }
 }
 
 // Launch everything staged as one step on compute stream k.
@@ -206,11 +211,14 @@ int launch_step(hb_server *s, int k)
 {
     auto st = std::make_unique<Step>();
     uint64_t n = 0;
-    size_t take = 0;
-    while (take < s->staged.size() && n + s->staged[take]->n <= kMaxStepN) n += s->staged[take++]->n;
-    if (take == 0) return HB_OK;
-    st->reqs.assign(s->staged.begin(), s->staged.begin() + take);
-    s->staged.erase(s->staged.begin(), s->staged.begin() + take);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        size_t take = 0;
+        while (take < s->staged.size() && n + s->staged[take]->n <= kMaxStepN) n += s->staged[take++]->n;
+        if (take == 0) return HB_OK;
+        st->reqs.assign(s->staged.begin(), s->staged.begin() + take);
+        s->staged.erase(s->staged.begin(), s->staged.begin() + take);
+    }
     st->n = n;
     st->algo = st->reqs[0]->algo;
     for (Req *r : st->reqs) st->mixed |= (r->algo < 0 || r->algo != st->algo);
@@ -228,7 +236,7 @@ int launch_step(hb_server *s, int k)
             hi[m] = uint8_t(r->algo < 0 ? r->algos[i] : r->algo);
             pos += r->lens[i];
         }
-        hipStreamWaitEvent(s->compute[k], r->copied, 0);
+        if (r->copied) hipStreamWaitEvent(s->compute[k], r->copied, 0);
         r->st = St::Launched;
     }
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
@@ -271,15 +279,16 @@ void finish_step(hb_server *s, int k, int status)
     uint64_t m = 0;
     for (Req *r : st->reqs) {
         const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
-        if (status == HB_OK) {
+        if (r->status == HB_OK) r->status = status;
+        if (r->status == HB_OK) {
             if (ds == stride) std::memcpy(r->out, hd + m * stride, r->n * stride);
             else
                 for (uint64_t i = 0; i < r->n; ++i) std::memcpy(r->out + i * ds, hd + (m + i) * stride, ds);
         }
         m += r->n;
         if (r->copied) {
-            r->t_h2d = status == HB_OK ? event_host_time(s, r->copied) : t;
-            s->ev_pool.push_back(r->copied);
+            r->t_h2d = r->status == HB_OK ? event_host_time(s, r->copied) : t;
+            hipEventDestroy(r->copied);
             r->copied = nullptr;
         }
         if (r->payload) s->arena.release(r->arena_off, r->payload);
@@ -289,7 +298,6 @@ void finish_step(hb_server *s, int k, int status)
         std::lock_guard<std::mutex> g(s->mu);
         for (Req *r : st->reqs) {
             r->t_done = t;
-            r->status = status;
             r->st = St::Done;
             s->slots_used--;
         }
@@ -304,13 +312,15 @@ void loop(hb_server *s)
     hipSetDevice(s->device);
     int next_stream = 0;
     for (;;) {
-        // 1. admission, in arrival order
-        std::vector<Req *> newly;
+        // 1. admission, in arrival order; admitted requests go to the staging threads
+        size_t admitted = 0;
+        bool have_staged = false;
         {
             std::unique_lock<std::mutex> g(s->mu);
             bool any_busy = false;
             for (auto &b : s->busy) any_busy |= bool(b);
-            if (s->pending.empty() && s->staged.empty() && !any_busy) {
+            if (s->pending.empty() && s->to_stage.empty() && s->staging_inflight == 0 && s->staged.empty() &&
+                !any_busy) {
                 if (s->stop) break;
                 s->cv_work.wait_for(g, std::chrono::milliseconds(50));
                 continue;
@@ -327,22 +337,19 @@ void loop(hb_server *s)
                 r->t_admit = s->now();
                 s->slots_used++;
                 s->pending.pop_front();
-                newly.push_back(r);
+                s->to_stage.push_back(r);
+                ++admitted;
             }
             if (!s->pending.empty() && !s->pending.front()->stalled) {
                 s->pending.front()->stalled = true;
                 s->stalls++;
             }
             if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
+            have_staged = !s->staged.empty();
         }
-        // 2. staging copies
-        for (Req *r : newly) {
-            int rc = stage_request(s, r);
-            if (rc != HB_OK) { s->fatal = rc; }
-            s->staged.push_back(r);
-        }
-        // 3. launch a step on a free compute stream
-        if (!s->staged.empty()) {
+        if (admitted) s->cv_stage.notify_all();
+        // 2. launch a step on a free compute stream
+        if (have_staged) {
             for (int t = 0; t < kStreams; ++t) {
                 const int k = (next_stream + t) % kStreams;
                 if (!s->busy[k]) {
@@ -359,7 +366,7 @@ void loop(hb_server *s)
                 }
             }
         }
-        // 4. completions
+        // 3. completions
         bool progressed = false;
         for (int k = 0; k < kStreams; ++k) {
             if (!s->busy[k]) continue;
@@ -367,7 +374,7 @@ void loop(hb_server *s)
             if (q == hipSuccess) { finish_step(s, k, HB_OK); progressed = true; }
             else if (q != hipErrorNotReady) { finish_step(s, k, HB_EHIP); progressed = true; }
         }
-        if (!progressed && newly.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (!progressed && !admitted) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -399,8 +406,14 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     };
     if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_arena), s->arena.capacity())) != hipSuccess)
         return fail(HB_ENOMEM, "hb_server_create: device arena", hipSuccess);
-    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->ring), kRingBytes, hipHostMallocDefault)) != hipSuccess)
-        return fail(HB_ENOMEM, "hb_server_create: pinned ring", hipSuccess);
+    for (Stager &g : s->stager) {
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&g.buf), 2 * kPiece, hipHostMallocDefault)) != hipSuccess)
+            return fail(HB_ENOMEM, "hb_server_create: pinned staging", hipSuccess);
+        if ((e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&g.half_free[0], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&g.half_free[1], hipEventDisableTiming)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: staging stream", e);
+    }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
     for (int k = 0; k < kStreams; ++k) {
@@ -419,6 +432,7 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
         return fail(HB_EHIP, "hb_server_create: reference event", e);
     s->ref_host = s->now();
     hb_server *p = s.release();
+    for (int w = 0; w < kStagers; ++w) p->stager[w].thr = std::thread(stager_loop, p, w);
     p->thr = std::thread(loop, p);
     *out = p;
     return HB_OK;
@@ -528,6 +542,21 @@ void hb_server_destroy(hb_server *s)
     }
     s->cv_work.notify_all();
     if (s->thr.joinable()) s->thr.join();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop_stagers = true;
+    }
+    s->cv_stage.notify_all();
+    for (Stager &g : s->stager) {
+        if (g.thr.joinable()) g.thr.join();
+        if (g.stream) {
+            hipStreamSynchronize(g.stream);
+            hipStreamDestroy(g.stream);
+        }
+        for (hipEvent_t e : g.half_free)
+            if (e) hipEventDestroy(e);
+        if (g.buf) hipHostFree(g.buf);
+    }
     for (int k = 0; k < kStreams; ++k) {
         if (s->compute[k]) hipStreamSynchronize(s->compute[k]);
         if (s->plan[k]) hb_plan_destroy(s->plan[k]);
@@ -539,10 +568,8 @@ void hb_server_destroy(hb_server *s)
         hipStreamSynchronize(s->copy_in);
         hipStreamDestroy(s->copy_in);
     }
-    for (auto &p : s->ring_live) hipEventDestroy(p.ev);
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
     if (s->ref) hipEventDestroy(s->ref);
-    if (s->ring) hipHostFree(s->ring);
     if (s->d_arena) hipFree(s->d_arena);
     delete s;
 }
