@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="fixed", choices=["fixed", "uneven", "mixed", "serve"])
+    p.add_argument("--workload", default="fixed", choices=["fixed", "uneven", "mixed", "serve", "digits9"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time in total")
     p.add_argument("--check", action="store_true", help="verify sampled digests against the oracle")
@@ -308,19 +308,48 @@ def bench_mixed(args, steps=3, warmup=1):
     return res
 
 
-def bench_serve(args, pool_size=256, seconds=15.0):
+def bench_digits9(args):
+    """The paper's workload (Sec. V-A.2): all 10^9 nine-character decimal strings, hashed
+    with each algorithm; the strings are generated on the device, digests written to HBM in
+    chunks of 2^27 (the output buffer is reused)."""
+    import torch
+
+    from paper_2407_09333_amd import hb
+
+    N, chunk = 1_000_000_000, 1 << 27
+    stream = torch.cuda.current_stream()
+    res = {"workload": "the 10^9 nine-character decimal strings 000000000..999999999 (9 B each), generated "
+                       "on the device; one padded block per message", "messages": N}
+    for a, name in enumerate(ALGO_NAMES):
+        out = torch.empty((chunk, hb.digest_size(a)), dtype=torch.uint8, device="cuda")
+        hb.hash_digits9(a, 0, chunk, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s0 in range(0, N, chunk):
+            hb.hash_digits9(a, s0, min(chunk, N - s0), out=out, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = {"ms": round(ms, 2), "Gmsg_per_s": round(N / ms / 1e6, 2),
+                     "payload_GBps": round(9 * N / ms / 1e6, 1),
+                     "in_plus_digest_GBps": round((9 + hb.digest_size(a)) * N / ms / 1e6, 1)}
+        del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9)):
     """Open-loop Poisson arrivals; each request 1..10,000 messages (log-uniform count),
     algorithm uniform over the three, lengths log-normal (median 256 B, cap 64 KiB); device
-    budget 64 GiB.  Capacity C is measured first with a saturating burst, then requests
-    arrive at 0.7 C; latency = completion time - scheduled arrival time."""
-    import threading
-
+    budget 64 GiB.  Capacity C is measured first with a saturating burst; then requests
+    arrive at 0.5 C, 0.7 C (the headline) and 0.9 C; latency = completion time - scheduled
+    arrival time (no coordinated omission)."""
     from paper_2407_09333_amd import hb, workloads
 
     pool = workloads.serving_requests(pool_size, 1.0, seed=5)
-    srv = hb.Server(hbm_budget_bytes=64 << 30, max_slots=512)
-    # warm-up and capacity: a burst of the whole pool
-    for r in pool[:16]:
+    srv = hb.Server(hbm_budget_bytes=64 << 30, max_slots=1024)
+    for r in pool[:16]:  # warm-up
         srv.wait(srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos))
     t0 = srv.now()
     ts = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in pool]
@@ -329,48 +358,58 @@ def bench_serve(args, pool_size=256, seconds=15.0):
     t1 = max(srv.times(t)["done"] for t in ts)
     cap_rps = len(pool) / (t1 - t0)
     cap_bytes = sum(int(r.lengths.sum()) for r in pool) / (t1 - t0)
-    rate = 0.7 * cap_rps
-    n_req = int(min(max(rate * seconds, 200), 50_000))
-    gaps = np.random.default_rng(105).exponential(1.0 / rate, size=n_req)
-    arrivals = np.cumsum(gaps)
-    tickets = [None] * n_req
-    sched = np.zeros(n_req)
-    start = srv.now() + 0.05
-    payload = 0
-    for k in range(n_req):
-        r = pool[k % pool_size]
-        target = start + arrivals[k]
-        while True:
-            d = target - srv.now()
-            if d <= 0:
-                break
-            if d > 0.002:
-                time.sleep(d - 0.001)
-        sched[k] = target
-        tickets[k] = srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)
-        payload += int(r.lengths.sum())
-    lat = np.zeros(n_req)
-    done_max = 0.0
-    for k, t in enumerate(tickets):
-        srv.wait(t)
-        tm = srv.times(t)
-        lat[k] = tm["done"] - sched[k]
-        done_max = max(done_max, tm["done"])
-    st = srv.stats()
+    runs = []
+    for frac in fractions:
+        rate = frac * cap_rps
+        n_req = int(min(max(rate * seconds / len(fractions), 200), 30_000))
+        arrivals = np.cumsum(np.random.default_rng(105).exponential(1.0 / rate, size=n_req))
+        tickets, sched = [None] * n_req, np.zeros(n_req)
+        s0 = srv.stats()
+        start = srv.now() + 0.05
+        payload = 0
+        for k in range(n_req):
+            r = pool[k % pool_size]
+            target = start + arrivals[k]
+            while True:
+                d = target - srv.now()
+                if d <= 0:
+                    break
+                if d > 0.002:
+                    time.sleep(d - 0.001)
+            sched[k] = target
+            tickets[k] = srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)
+            payload += int(r.lengths.sum())
+        lat = np.zeros(n_req)
+        phases = np.zeros((n_req, 3))
+        done_max = 0.0
+        for k, t in enumerate(tickets):
+            srv.wait(t)
+            tm = srv.times(t)
+            lat[k] = tm["done"] - sched[k]
+            phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
+            done_max = max(done_max, tm["done"])
+        s1 = srv.stats()
+        runs.append({"load_fraction": frac, "offered_req_per_s": round(rate, 1), "requests": n_req,
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "p999_ms": round(float(np.percentile(lat, 99.9)) * 1e3, 3),
+                     "achieved_GBps": round(payload / (done_max - start) / 1e9, 3),
+                     "steps": s1["steps"] - s0["steps"], "admission_stalls": s1["stalls"] - s0["stalls"],
+                     "median_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.median(phases, 0)]})
+        print(f"bench: serving at {frac} C: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+    peak = srv.stats()["peak_bytes"]
     srv.close()
+    head = next(r for r in runs if r["load_fraction"] == 0.7) if 0.7 in fractions else runs[-1]
     return {
         "workload": "Poisson arrivals; 1..10,000 messages per request (log-uniform), algorithm uniform, "
-                    "lengths log-normal (median 256 B, sigma 1.5, cap 64 KiB); payload in host memory; "
-                    "device budget 64 GiB",
+                    "lengths log-normal (median 256 B, sigma 1.5, cap 64 KiB); payload in host memory "
+                    "(PCIe- and host-copy-inclusive); device budget 64 GiB",
         "capacity_req_per_s": round(cap_rps, 1), "capacity_GBps": round(cap_bytes / 1e9, 3),
-        "offered_req_per_s": round(rate, 1), "requests": n_req,
-        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-        "p999_ms": round(float(np.percentile(lat, 99.9)) * 1e3, 3),
-        "achieved_GBps": round(payload / (done_max - start) / 1e9, 3),
-        "steps": st["steps"], "admission_stalls": st["stalls"], "peak_resident_bytes": st["peak_bytes"],
+        "offered_req_per_s": head["offered_req_per_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "p999_ms": head["p999_ms"], "achieved_GBps": head["achieved_GBps"],
+        "sweep": runs, "peak_resident_bytes": peak,
     }
-
 
 def main():
     args = parse()
@@ -387,12 +426,16 @@ def main():
             rec["batched_uneven"] = bench_uneven(args)
             print("bench: mixed 8 GiB", file=sys.stderr, flush=True)
             rec["batched_mixed"] = bench_mixed(args)
+            print("bench: paper workload (10^9 nine-digit strings)", file=sys.stderr, flush=True)
+            rec["paper_workload_digits9"] = bench_digits9(args)
             print("bench: serving", file=sys.stderr, flush=True)
             rec["serving"] = bench_serve(args, seconds=args.serve_seconds)
     elif args.workload == "uneven":
         rec = {"batched_uneven": bench_uneven(args, steps=args.steps, warmup=args.warmup)}
     elif args.workload == "mixed":
         rec = {"batched_mixed": bench_mixed(args, steps=args.steps, warmup=args.warmup)}
+    elif args.workload == "digits9":
+        rec = {"paper_workload_digits9": bench_digits9(args)}
     else:
         rec = {"serving": bench_serve(args, seconds=args.serve_seconds)}
     print(json.dumps(rec), flush=True)

@@ -89,6 +89,16 @@ int hash_batch_fixed(int algo, const uint8_t *messages, uint64_t n, uint64_t msg
 int hash_batch_mixed(const uint8_t *algos, const uint8_t *messages, const uint64_t *offsets,
                      const uint64_t *lengths, uint64_t n, uint8_t *digests_out, void *stream);
 
+/*
+ * hash_digits9 -- the paper's own workload (Sec. V-A.2): the digests of the 9-character
+ * decimal strings "000000000" .. "999999999".  Message i is the zero-padded decimal text
+ * of start + i; the text is generated on the device, so no input buffer exists.
+ *   start, n     0 <= start, start + n <= 10^9
+ *   digests_out  device, n slots of hb_digest_size(algo) bytes
+ * Allocates nothing.
+ */
+int hash_digits9(int algo, uint64_t start, uint64_t n, uint8_t *digests_out, void *stream);
+
 /* ------------------------------------------------------------------------------------ */
 /* Batched form: length-bucketed, longest-first, persistent fused launch in a hipGraph.  */
 /* ------------------------------------------------------------------------------------ */
@@ -98,13 +108,19 @@ typedef struct hb_plan hb_plan;
 enum {
     HB_PLAN_GRAPH = 1,      /* capture the pipeline in a hipGraph and replay it (default on) */
     HB_PLAN_AUTOTUNE = 2,   /* time the kernel variants on first use and cache the choice */
-    HB_PLAN_NO_SORT = 4     /* skip bucketing: lanes take messages in index order */
+    HB_PLAN_NO_SORT = 4,    /* skip bucketing: lanes take messages in index order */
+    HB_PLAN_NO_LONG = 8     /* no separate long-chain path (see hb_plan_create) */
 };
 
 /*
  * hb_plan_create -- reserve device workspace for batches of up to max_n messages and
- * build the launch plan.  The plan owns its workspace (about 24 bytes per message plus
- * a fixed part) and, with HB_PLAN_GRAPH, a hipGraph captured on first run.
+ * build the launch plan.  The plan owns its workspace (about 4 bytes per message, a fixed
+ * part of about 0.6 MB, and -- unless HB_PLAN_NO_LONG -- a long-chain scratch of
+ * HB_LONG_SCRATCH_MB MiB, default 256) and, with HB_PLAN_GRAPH, a hipGraph captured on
+ * first run.  Long-chain path: messages of at least HB_LONG_MIN_BLOCKS blocks (default 256,
+ * i.e. about 16 KiB) have every block's schedule words computed block-parallel first, then
+ * run as rounds-only chains in a high-priority kernel beside the bulk kernel (a message's
+ * blocks are strictly sequential, so this shortens the critical path, not the work).
  * Returns HB_ENOMEM if the workspace cannot be allocated.
  */
 int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags);

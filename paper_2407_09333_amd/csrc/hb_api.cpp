@@ -120,4 +120,15 @@ int hash_batch_mixed(const uint8_t *algos, const uint8_t *messages, const uint64
     return HB_OK;
 }
 
+int hash_digits9(int algo, uint64_t start, uint64_t n, uint8_t *digests_out, void *stream)
+{
+    int rc = check_common(algo, digests_out ? digests_out : nullptr, n, digests_out, uint64_t(digest_size(algo)),
+                          "hash_digits9");
+    if (rc != HB_OK || n == 0) return rc;
+    if (start >= 1000000000ull || n > 1000000000ull - start)
+        return set_error(HB_EINVAL, "hash_digits9: start + n must not exceed 10^9 (nine decimal digits)");
+    hipError_t e = launch_digits9(algo, start, n, digests_out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HB_OK : hip_error(e, "hash_digits9: launch");
+}
+
 }  // extern "C"

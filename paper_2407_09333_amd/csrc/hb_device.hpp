@@ -256,6 +256,19 @@ template <int A> __device__ __forceinline__ Msg make_msg(const uint8_t *base, ui
     return m;
 }
 
+// The 17 dwords covering whole block blk (the 17th holds message bytes only when r != 0;
+// for r == 0 dword 15 is re-read in its place, so no read leaves the message's dwords).
+__device__ __forceinline__ void load_raw_block(const Msg &m, uint64_t blk, uint32_t raw[17])
+{
+    const HB_GLOBAL uint32_t *q = m.p + blk * 16u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u32x4 v = *reinterpret_cast<const HB_GLOBAL u32x4_a4 *>(q + 4 * k);
+        raw[4 * k + 0] = v.x; raw[4 * k + 1] = v.y; raw[4 * k + 2] = v.z; raw[4 * k + 3] = v.w;
+    }
+    raw[16] = q[m.r ? 16 : 15];
+}
+
 // Block blk lies wholly inside the message: 16 words from 17 dwords (the 17th holds
 // message bytes only when r != 0; for r == 0 dword 15 is re-read in its place).
 __device__ __forceinline__ void load_full_block(const Msg &m, uint64_t blk, uint32_t w[16])
@@ -360,6 +373,31 @@ __device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, 
         uint32_t w[16];
         if (blk < nfast) load_full_block(m, blk, w);
         else load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
+        compress<A>(s, w);
+    }
+}
+
+// As hash_message, with the next whole block's loads issued before the current block is
+// compressed, so a lane's memory latency is hidden behind its own compression even when
+// few waves share the SIMD.  Costs 17 VGPRs.
+template <int A>
+__device__ __forceinline__ void hash_message_prefetch(const uint8_t *base, uint64_t len, uint32_t s[8])
+{
+    const Msg m = make_msg<A>(base, len);
+    const uint64_t nb = (len + 8u) / 64u + 1u;
+    const uint64_t nfast = len / 64u;
+    init_state<A>(s);
+    uint32_t raw[17];
+    if (nfast > 0) load_raw_block(m, 0, raw);
+    for (uint64_t blk = 0; blk < nb; ++blk) {
+        uint32_t w[16];
+        if (blk < nfast) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) w[i] = perm(raw[i + 1], raw[i], m.sel);
+            if (blk + 1 < nfast) load_raw_block(m, blk + 1, raw);
+        } else {
+            load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
+        }
         compress<A>(s, w);
     }
 }

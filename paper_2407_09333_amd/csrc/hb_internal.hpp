@@ -22,4 +22,7 @@ hipError_t launch_plain(int algo, const uint8_t *msgs, const uint64_t *offs, con
 
 int digest_size(int algo);
 
+// The paper's 9-digit decimal workload, generated on the device (see hash_digits9).
+hipError_t launch_digits9(int algo, uint64_t start, uint64_t n, uint8_t *out, hipStream_t stream);
+
 }  // namespace hb

@@ -37,6 +37,56 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(const uint8_t *__restrict
     store_digest<A>(out + i * stride, s, stride);
 }
 
+// The paper's workload (Sec. V-A.2): message i is the 9-character decimal text of
+// start + i, zero-padded ("000000000" .. "999999999").  The text is produced in registers,
+// so a 9-byte message is one padded block: 9 bytes, 0x80, zeros, bit length 72.
+template <int A>
+__global__ __launch_bounds__(kPlainBlock) void k_digits9(uint64_t start, uint64_t n, uint8_t *__restrict__ out)
+{
+    const uint64_t i = uint64_t(blockIdx.x) * kPlainBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t v = uint32_t(start + i);  // < 10^9
+    uint32_t d[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) {
+        const uint32_t q = v / 10u;
+        d[k] = 0x30u + (v - q * 10u);
+        v = q;
+    }
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = 0u;
+    if (Traits<A>::kBE) {
+        w[0] = (d[0] << 24) | (d[1] << 16) | (d[2] << 8) | d[3];
+        w[1] = (d[4] << 24) | (d[5] << 16) | (d[6] << 8) | d[7];
+        w[2] = (d[8] << 24) | 0x00800000u;
+        w[15] = 72u;
+    } else {
+        w[0] = d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24);
+        w[1] = d[4] | (d[5] << 8) | (d[6] << 16) | (d[7] << 24);
+        w[2] = d[8] | 0x8000u;
+        w[14] = 72u;
+    }
+    uint32_t s[8];
+    init_state<A>(s);
+    compress<A>(s, w);
+    store_digest<A>(out + i * Traits<A>::kDigest, s, Traits<A>::kDigest);
+}
+
+hipError_t launch_digits9(int algo, uint64_t start, uint64_t n, uint8_t *out, hipStream_t stream)
+{
+    const uint64_t blocks = (n + kPlainBlock - 1) / kPlainBlock;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+    const dim3 grid{uint32_t(blocks), 1, 1}, block{kPlainBlock, 1, 1};
+    switch (algo) {
+    case MD5: hipLaunchKernelGGL(k_digits9<MD5>, grid, block, 0, stream, start, n, out); break;
+    case SHA1: hipLaunchKernelGGL(k_digits9<SHA1>, grid, block, 0, stream, start, n, out); break;
+    case SM3: hipLaunchKernelGGL(k_digits9<SM3>, grid, block, 0, stream, start, n, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int A>
 static hipError_t launch_a(const uint8_t *msgs, const uint64_t *offs, const uint64_t *lens, uint64_t n,
                            bool fixed, uint64_t fixed_len, uint8_t *out, uint32_t stride,

@@ -18,6 +18,7 @@
 #include "../../include/hb.h"
 #include "hb_device.hpp"
 #include "hb_internal.hpp"
+#include "hb_long.hpp"
 
 namespace hb {
 
@@ -48,6 +49,7 @@ struct PlanDesc {
     int32_t algo;             // used when algos == nullptr
     int32_t sort;             // 0: one key per algorithm (index order within it)
     int32_t mpl;              // messages per lane per item
+    uint32_t long_min_key;    // messages with key >= this run as long chains (0: off)
 };
 
 // Meta block (device): segment bookkeeping filled by k_scan / k_items.
@@ -58,6 +60,10 @@ struct PlanMeta {
     uint32_t queue;           // next item to hand out
     uint32_t pad;
     unsigned long long total_cost;
+    uint32_t long_n[3];       // long-chain messages per algorithm (a prefix of its segment)
+    uint32_t long_first[4];   // first long-lane index of each algorithm (padded to 64 lanes)
+    uint32_t long_blocks;     // scratch blocks in use
+    uint32_t max_key;         // largest key present (scans stop there)
 };
 
 // Device workspace (pointers fixed for the plan's life).
@@ -69,8 +75,16 @@ struct PlanWs {
     uint32_t *bin_start;      // 3 * kBins first sorted position of each key
     uint32_t *sorted;         // message indices, per-algorithm segments, padded to items
     uint32_t *order;          // item ids, longest first
+    uint32_t *long_base;      // per long lane: first scratch block of its message
+    uint32_t *sched;          // scratch: kSchedWords words per block of long messages
+    uint32_t sched_blocks;    // scratch capacity in blocks
+    uint32_t max_long_lanes;  // capacity of long_base
     uint64_t max_n;
 };
+
+// Long chains are scheduled in this algorithm order (most work per block first) when the
+// scratch cannot hold all of them: slot 0 = SM3, 1 = SHA-1, 2 = MD5.
+__host__ __device__ constexpr int long_order(int o) { return o == 0 ? SM3 : (o == 1 ? SHA1 : MD5); }
 
 __device__ __forceinline__ uint32_t msg_key(uint64_t len, int sort)
 {
@@ -103,7 +117,10 @@ __global__ __launch_bounds__(kThreads) void k_zero(PlanWs ws)
     for (uint32_t i = t; i < 3 * kBins; i += step) { ws.hist[i] = 0; ws.cursor[i] = 0; }
     if (t == 0) {
         PlanMeta *m = ws.meta;
-        for (int a = 0; a < 3; ++a) m->count[a] = 0;
+        for (int a = 0; a < 3; ++a) { m->count[a] = 0; m->long_n[a] = 0; m->long_first[a] = 0; }
+        m->long_first[3] = 0;
+        m->long_blocks = 0;
+        m->max_key = 0;
         m->queue = 0;
         m->total_cost = 0;
     }
@@ -114,8 +131,11 @@ __global__ __launch_bounds__(kThreads) void k_zero(PlanWs ws)
 __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
 {
     __shared__ uint32_t lh[3 * kLdsKeys];
+    __shared__ uint32_t lmax;
     const PlanDesc d = *ws.desc;
     for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) lh[i] = 0;
+    if (threadIdx.x == 0) lmax = 0;
+    uint32_t my_max = 0;
     __syncthreads();
     const uint64_t step = uint64_t(gridDim.x) * kThreads;
     for (uint64_t base = uint64_t(blockIdx.x) * kThreads; base < d.n; base += step) {
@@ -124,6 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
             const int a = msg_algo(d, i);
             if (a >= 0 && a < 3) {
                 const uint32_t key = msg_key(d.lens[i], d.sort);
+                my_max = key > my_max ? key : my_max;
                 const uint32_t slot = uint32_t(a) * kBins + key;
                 const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
                 const uint64_t same = __ballot(slot == first);
@@ -139,11 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
             }
         }
     }
+    if (my_max) atomicMax(&lmax, my_max);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) {
         const uint32_t c = lh[i];
         if (c) atomicAdd(&ws.hist[(i / kLdsKeys) * kBins + (i % kLdsKeys)], c);
     }
+    if (threadIdx.x == 0 && lmax) atomicMax(&ws.meta->max_key, lmax);
 }
 
 // Exclusive scan, longest key first within each algorithm; segments padded to whole
@@ -154,15 +177,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(PlanWs ws)
     __shared__ uint32_t seg_base;
     const PlanDesc d = *ws.desc;
     const uint32_t per_item = 64u * uint32_t(d.mpl);
-    constexpr uint32_t kPer = (kBins + kScanThreads - 1) / kScanThreads;
+    const uint32_t top = ws.meta->max_key;        // keys above it are empty
+    const uint32_t nkeys = top + 1;
+    const uint32_t kPer = (nkeys + kScanThreads - 1) / kScanThreads;
     if (threadIdx.x == 0) seg_base = 0;
     __syncthreads();
     for (int a = 0; a < 3; ++a) {
-        // thread t owns reversed keys [t*kPer, (t+1)*kPer): key = kBins - 1 - r
+        // thread t owns reversed keys [t*kPer, (t+1)*kPer): key = top - r
         uint32_t local = 0;
         for (uint32_t k = 0; k < kPer; ++k) {
             const uint32_t r = threadIdx.x * kPer + k;
-            if (r < kBins) local += ws.hist[a * kBins + (kBins - 1 - r)];
+            if (r < nkeys) local += ws.hist[a * kBins + (top - r)];
         }
         part[threadIdx.x] = local;
         __syncthreads();
@@ -176,8 +201,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(PlanWs ws)
         uint32_t run = seg_base + part[threadIdx.x] - local;
         for (uint32_t k = 0; k < kPer; ++k) {
             const uint32_t r = threadIdx.x * kPer + k;
-            if (r < kBins) {
-                const uint32_t key = kBins - 1 - r;
+            if (r < nkeys) {
+                const uint32_t key = top - r;
                 ws.bin_start[a * kBins + key] = run;
                 run += ws.hist[a * kBins + key];
             }
@@ -326,18 +351,191 @@ __global__ __launch_bounds__(kThreads) void k_zero_invalid(PlanWs ws)
     }
 }
 
-template <int A>
+// Choose the long-chain messages: within each algorithm's segment, the leading messages
+// (longest first) whose key reaches long_min_key, while their blocks fit the scratch;
+// assign each its first scratch block.  One workgroup; lanes padded to 64 per algorithm
+// so each long-chain wave is algorithm-uniform.
+__global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
+{
+    __shared__ uint32_t part[kScanThreads];
+    __shared__ uint32_t s_run, s_lane, s_stop;
+    const PlanDesc d = *ws.desc;
+    PlanMeta *m = ws.meta;
+    if (threadIdx.x == 0) { s_run = 0; s_lane = 0; }
+    __syncthreads();
+    for (int o = 0; o < 3; ++o) {
+        const int a = long_order(o);
+        uint32_t cand = 0;
+        if (d.long_min_key && d.sort) {
+            // messages with key >= long_min_key: a prefix of the segment
+            uint32_t local = 0;
+            for (uint32_t k = d.long_min_key + threadIdx.x; k <= m->max_key; k += kScanThreads)
+                local += ws.hist[a * kBins + k];
+            part[threadIdx.x] = local;
+            __syncthreads();
+            for (uint32_t off = kScanThreads / 2; off > 0; off >>= 1) {
+                if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+                __syncthreads();
+            }
+            cand = part[0];
+            __syncthreads();
+        }
+        const uint32_t lane0 = s_lane;
+        const uint32_t lane_cap = ws.max_long_lanes;
+        if (threadIdx.x == 0) s_stop = 0;
+        __syncthreads();
+        uint32_t taken = 0;
+        for (uint32_t c0 = 0; c0 < cand; c0 += kScanThreads) {
+            if (s_stop) break;
+            const uint32_t i = c0 + threadIdx.x;
+            uint32_t nb = 0;
+            if (i < cand) {
+                const uint32_t idx = ws.sorted[m->seg_pos[a] + i];
+                nb = uint32_t((d.lens[idx] + 8u) / 64u + 1u);
+            }
+            part[threadIdx.x] = nb;
+            __syncthreads();
+            for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+                const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+                __syncthreads();
+                part[threadIdx.x] += v;
+                __syncthreads();
+            }
+            const uint64_t base = uint64_t(s_run) + part[threadIdx.x] - nb;
+            const bool fits = i < cand && base + nb <= ws.sched_blocks && lane0 + i + 64 * (3 - o) < lane_cap;
+            if (fits) ws.long_base[lane0 + i] = uint32_t(base);
+            const uint32_t nfit = uint32_t(__syncthreads_count(fits));
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (nfit) s_run += part[nfit - 1];
+                if (nfit < kScanThreads) s_stop = 1;
+            }
+            taken += nfit;
+            __syncthreads();
+        }
+        const uint32_t padded = (taken + 63u) / 64u * 64u;
+        for (uint32_t i = taken + threadIdx.x; i < padded; i += kScanThreads) ws.long_base[lane0 + i] = s_run;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            m->long_n[a] = taken;
+            m->long_first[a] = lane0;
+            s_lane = lane0 + padded;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        m->long_first[3] = s_lane;  // end of the long lanes (not indexed by algorithm)
+        m->long_blocks = s_run;
+    }
+}
+
+// Which algorithm long lane g (< long_first[3]) belongs to; i = its index in that algorithm.
+__device__ __forceinline__ int long_algo(const PlanMeta &m, uint32_t g, uint32_t &i)
+{
+    for (int o = 0; o < 3; ++o) {
+        const int a = long_order(o);
+        const uint32_t end = o < 2 ? m.long_first[long_order(o + 1)] : m.long_first[3];
+        if (g >= m.long_first[a] && g < end) {
+            i = g - m.long_first[a];
+            return a;
+        }
+    }
+    i = 0xffffffffu;
+    return MD5;
+}
+
+// Schedule words of every block of every long-chain message: one lane per block.
+__global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
+{
+    const PlanDesc d = *ws.desc;
+    const PlanMeta m = *ws.meta;
+    const uint32_t total = m.long_blocks, lanes = m.long_first[3];
+    for (uint32_t gb = blockIdx.x * kThreads + threadIdx.x; gb < total; gb += gridDim.x * kThreads) {
+        // last long lane whose first block is <= gb (padding lanes repeat the next base)
+        uint32_t lo = 0, hi = lanes;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (ws.long_base[mid] <= gb) lo = mid;
+            else hi = mid;
+        }
+        uint32_t i = 0;
+        const int a = long_algo(m, lo, i);
+        if (i >= m.long_n[a]) continue;  // a padding lane: cannot be the last lane at or below gb
+        const uint32_t idx = ws.sorted[m.seg_pos[a] + i];
+        const uint64_t len = d.lens[idx];
+        const uint64_t nb = (len + 8u) / 64u + 1u, blk = gb - ws.long_base[lo];
+        if (blk >= nb) continue;
+        uint32_t w[16], out[kSchedWords];
+        uint32_t *dst = ws.sched + uint64_t(gb) * kSchedWords;
+        HB_GLOBAL u32x4 *q = reinterpret_cast<HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(dst));
+#define HB_SCHED_CASE(A)                                                                          \
+        {                                                                                         \
+            const Msg mm = make_msg<A>(d.msgs + d.offs[idx], len);                                \
+            if (blk < len / 64u) load_full_block(mm, blk, w);                                     \
+            else load_any_block<Traits<A>::kBE>(mm, blk, blk + 1 == nb, w);                       \
+            sched_block<A>(w, out);                                                               \
+            for (int k = 0; k < SchedWords<A>::kN / 4; ++k)                                       \
+                q[k] = u32x4{out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]};          \
+        }
+        if (a == MD5) HB_SCHED_CASE(MD5)
+        else if (a == SHA1) HB_SCHED_CASE(SHA1)
+        else HB_SCHED_CASE(SM3)
+#undef HB_SCHED_CASE
+    }
+}
+
+// Long chains, one lane per message, at the highest wave priority; each wave's lanes are
+// of one algorithm.  SCHED = 1: rounds only, from the precomputed words; SCHED = 0: the
+// ordinary compression reading the message with the next block prefetched.
+template <int SCHED>
+__global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
+{
+    const PlanDesc d = *ws.desc;
+    const PlanMeta m = *ws.meta;
+    const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t wave_first = g & ~63u;
+    if (wave_first >= m.long_first[3]) return;
+    uint32_t i = 0;
+    const int a = long_algo(m, wave_first, i);
+    i = g - m.long_first[a];
+    if (i >= m.long_n[a]) return;  // padding lane
+    __builtin_amdgcn_s_setprio(3);
+    const uint32_t idx = ws.sorted[m.seg_pos[a] + i];
+    const uint64_t nb = (d.lens[idx] + 8u) / 64u + 1u;
+    uint32_t st[8];
+    uint8_t *out = d.out + uint64_t(idx) * d.stride;
+    if constexpr (SCHED) {
+        const uint32_t *src = ws.sched + uint64_t(ws.long_base[g]) * kSchedWords;
+        if (a == MD5) { chain_from_sched<MD5>(src, nb, st); store_digest<MD5>(out, st, d.stride); }
+        else if (a == SHA1) { chain_from_sched<SHA1>(src, nb, st); store_digest<SHA1>(out, st, d.stride); }
+        else { chain_from_sched<SM3>(src, nb, st); store_digest<SM3>(out, st, d.stride); }
+    } else {
+        const uint8_t *msg = d.msgs + d.offs[idx];
+        const uint64_t len = d.lens[idx];
+        if (a == MD5) { hash_message<MD5>(msg, len, st); store_digest<MD5>(out, st, d.stride); }
+        else if (a == SHA1) { hash_message_prefetch<SHA1>(msg, len, st); store_digest<SHA1>(out, st, d.stride); }
+        else { hash_message_prefetch<SM3>(msg, len, st); store_digest<SM3>(out, st, d.stride); }
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
+template <int A, int PF>
 __device__ __forceinline__ void hash_lane(const PlanDesc &d, uint32_t idx)
 {
     uint32_t s[8];
-    hash_message<A>(d.msgs + d.offs[idx], d.lens[idx], s);
+    const uint64_t off = reinterpret_cast<const HB_GLOBAL uint64_t *>(reinterpret_cast<uintptr_t>(d.offs))[idx];
+    const uint64_t len = reinterpret_cast<const HB_GLOBAL uint64_t *>(reinterpret_cast<uintptr_t>(d.lens))[idx];
+    if constexpr (PF && A != MD5) hash_message_prefetch<A>(d.msgs + off, len, s);
+    else hash_message<A>(d.msgs + off, len, s);
     store_digest<A>(d.out + uint64_t(idx) * d.stride, s, d.stride);
 }
 
 // Persistent fused kernel: each wave takes items from the queue until none are left.
 // An item is 64 * mpl sorted positions of one algorithm; lane l hashes positions
 // l, l + 64, ... of it.  Items whose cost exceeds the average per-wave share run at raised
-// wave priority so the longest chains keep their issue slots.
+// wave priority so the longest chains keep their issue slots.  PF = 1 prefetches the next
+// block of SHA-1 / SM3 messages (MD5 already reads two blocks per burst).
+template <int PF>
 __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
 {
     const PlanDesc d = *ws.desc;
@@ -361,12 +559,16 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
         const uint64_t cost = first == kInvalid ? 0 : uint64_t(msg_key(d.lens[first], d.sort)) * algo_cost(a) * d.mpl;
         if (cost > share) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
+        const uint32_t long_end = mp->seg_pos[a] + mp->long_n[a];  // handled by k_hash_long
+        if (pos0 + per_item <= long_end) continue;
         for (int j = 0; j < d.mpl; ++j) {
-            const uint32_t idx = ws.sorted[pos0 + uint32_t(j) * 64u + lane];
+            const uint32_t pos = pos0 + uint32_t(j) * 64u + lane;
+            if (pos < long_end) continue;
+            const uint32_t idx = ws.sorted[pos];
             if (idx == kInvalid) continue;
-            if (a == MD5) hash_lane<MD5>(d, idx);
-            else if (a == SHA1) hash_lane<SHA1>(d, idx);
-            else hash_lane<SM3>(d, idx);
+            if (a == MD5) hash_lane<MD5, PF>(d, idx);
+            else if (a == SHA1) hash_lane<SHA1, PF>(d, idx);
+            else hash_lane<SM3, PF>(d, idx);
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -393,6 +595,7 @@ struct TuneKey {
 struct TuneChoice {
     int waves_per_cu;
     int mpl;
+    int variant;
 };
 
 static std::mutex g_tune_mu;
@@ -400,7 +603,7 @@ static std::map<TuneKey, TuneChoice> g_tune_cache;
 static bool g_tune_loaded = false;
 
 // Optional persistence: HB_TUNE_CACHE names a text file of lines
-// "arch cus algo_mask bucket waves_per_cu msgs_per_lane".
+// "arch cus algo_mask bucket waves_per_cu msgs_per_lane variant".
 static void load_tune_cache()
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -411,9 +614,10 @@ static void load_tune_cache()
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     char arch[64];
-    int cus, mask, bucket, w, m;
-    while (std::fscanf(f, "%63s %d %d %d %d %d", arch, &cus, &mask, &bucket, &w, &m) == 6)
-        if (w > 0 && w <= 64 && m > 0 && m <= kMaxMpl) g_tune_cache[TuneKey{arch, cus, mask, bucket}] = TuneChoice{w, m};
+    int cus, mask, bucket, w, m, v;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d", arch, &cus, &mask, &bucket, &w, &m, &v) == 7)
+        if (w > 0 && w <= 64 && m > 0 && m <= kMaxMpl && (v == 0 || v == 1))
+            g_tune_cache[TuneKey{arch, cus, mask, bucket}] = TuneChoice{w, m, v};
     std::fclose(f);
 }
 
@@ -425,8 +629,8 @@ static void save_tune_cache()
     FILE *f = std::fopen(path, "w");
     if (!f) return;
     for (auto &kv : g_tune_cache)
-        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.arch.c_str(), kv.first.cus, kv.first.algo_mask,
-                     kv.first.len_bucket, kv.second.waves_per_cu, kv.second.mpl);
+        std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.arch.c_str(), kv.first.cus, kv.first.algo_mask,
+                     kv.first.len_bucket, kv.second.waves_per_cu, kv.second.mpl, kv.second.variant);
     std::fclose(f);
 }
 
@@ -447,6 +651,11 @@ struct hb_plan {
     hipGraphExec_t exec = nullptr;
     int graph_mpl = 0, graph_sort = -1;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;  // hash-kernel timing
+    bool long_on = false;           // long-chain path enabled
+    bool long_sched = true;         // precomputed schedule words (else direct reads)
+    uint32_t long_min_key = 0;
+    hipStream_t side = nullptr;     // long-chain kernel runs here, beside the persistent kernel
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double kernel_ms_sum = 0.0;
     int kernel_ms_count = 0;
     void *alloc = nullptr;
@@ -508,8 +717,25 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
     const int hash_blocks = (p->cus * p->waves_per_cu + 3) / 4;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (timed) ev = take_events(p);
+    if (p->long_on) {
+        hipLaunchKernelGGL(k_long_scan, dim3(1), dim3(kScanThreads), 0, s, ws);
+        if (p->long_sched) hipLaunchKernelGGL(k_sched, dim3(g), dim3(kThreads), 0, s, ws);
+    }
     if (ev.first) hipEventRecord(ev.first, s);
-    hipLaunchKernelGGL(k_hash_persistent, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+    if (p->long_on) {
+        // fork: the long chains start first on the side stream and run beside the bulk
+        hipEventRecord(p->ev_fork, s);
+        hipStreamWaitEvent(p->side, p->ev_fork, 0);
+        const int long_blocks = int((ws.max_long_lanes + kThreads - 1) / kThreads);
+        if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
+        else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
+        hipEventRecord(p->ev_join, p->side);
+    }
+    if (p->variant == 1)
+        hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+    else
+        hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+    if (p->long_on) hipStreamWaitEvent(s, p->ev_join, 0);  // join
     if (ev.first) {
         hipEventRecord(ev.second, s);
         p->ev_pending.push_back(ev);
@@ -560,21 +786,25 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
         if (it != g_tune_cache.end()) {
             p->waves_per_cu = it->second.waves_per_cu;
             p->mpl = it->second.mpl;
+            p->variant = it->second.variant;
             return HB_OK;
         }
     }
     const int flags_saved = p->flags;
     p->flags &= ~HB_PLAN_GRAPH;
     float best = 1e30f;
-    TuneChoice bestc{p->waves_per_cu, p->mpl};
+    TuneChoice bestc{p->waves_per_cu, p->mpl, p->variant};
     const int wpcs[] = {8, 16, 32};
     const int mpls[] = {1, 2};
+    const int variants[] = {0, 1};
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
+    for (int var : variants)
     for (int mpl : mpls) {
         for (int w : wpcs) {
             p->waves_per_cu = w;
+            p->variant = var;
             PlanDesc d = d0;
             d.mpl = mpl;
             p->mpl = mpl;
@@ -589,7 +819,7 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
                 hipEventElapsedTime(&ms, a, b);
                 if (rep) tot += ms;  // first repetition is a warm-up
             }
-            if (tot < best) { best = tot; bestc = TuneChoice{w, mpl}; }
+            if (tot < best) { best = tot; bestc = TuneChoice{w, mpl, var}; }
         }
     }
     hipEventDestroy(a);
@@ -600,6 +830,7 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
     p->flags = flags_saved;
     p->waves_per_cu = bestc.waves_per_cu;
     p->mpl = bestc.mpl;
+    p->variant = bestc.variant;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = bestc;
@@ -635,7 +866,24 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     const uint64_t sz_desc = up(sizeof(PlanDesc)), sz_meta = up(sizeof(PlanMeta));
     const uint64_t sz_bins = up(3ull * kBins * 4);
     const uint64_t sz_sorted = up(sorted_cap * 4), sz_order = up(items_cap * 4);
-    const uint64_t total = sz_desc + sz_meta + 3 * sz_bins + sz_sorted + sz_order;
+    // long-chain scratch: HB_LONG_SCRATCH_MB (default 256) of precomputed block words for
+    // messages of at least HB_LONG_MIN_BLOCKS (default 256) blocks
+    p->long_on = !(flags & HB_PLAN_NO_LONG) && !(flags & HB_PLAN_NO_SORT);
+    uint64_t scratch_mb = 256, min_blocks = 256;
+    if (const char *v = std::getenv("HB_LONG_SCRATCH_MB")) scratch_mb = std::strtoull(v, nullptr, 10);
+    if (const char *v = std::getenv("HB_LONG_MIN_BLOCKS")) min_blocks = std::strtoull(v, nullptr, 10);
+    if (scratch_mb == 0 || min_blocks < 2 || min_blocks >= kBins) p->long_on = false;
+    if (const char *v = std::getenv("HB_LONG_MODE")) p->long_sched = std::strcmp(v, "direct") != 0;
+    uint64_t sched_blocks = 0, long_lanes = 0, scratch_blocks = 0;
+    if (p->long_on) {
+        // direct mode needs no scratch: the block budget only bounds how many lanes are long
+        sched_blocks = std::min<uint64_t>(scratch_mb * (1ull << 20) / (kSchedWords * 4), 0xffffffffull);
+        long_lanes = sched_blocks / min_blocks + 4 * 64;
+        scratch_blocks = p->long_sched ? sched_blocks : 0;
+        p->long_min_key = uint32_t(min_blocks);
+    }
+    const uint64_t sz_long = up(long_lanes * 4), sz_sched = up(scratch_blocks * kSchedWords * 4);
+    const uint64_t total = sz_desc + sz_meta + 3 * sz_bins + sz_sorted + sz_order + sz_long + sz_sched;
     e = hipMalloc(&p->alloc, total);
     if (e != hipSuccess) { delete p; return set_error(HB_ENOMEM, "hb_plan_create: workspace allocation failed"); }
     char *c = static_cast<char *>(p->alloc);
@@ -645,9 +893,22 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     p->ws.cursor = reinterpret_cast<uint32_t *>(c); c += sz_bins;
     p->ws.bin_start = reinterpret_cast<uint32_t *>(c); c += sz_bins;
     p->ws.sorted = reinterpret_cast<uint32_t *>(c); c += sz_sorted;
-    p->ws.order = reinterpret_cast<uint32_t *>(c);
+    p->ws.order = reinterpret_cast<uint32_t *>(c); c += sz_order;
+    p->ws.long_base = reinterpret_cast<uint32_t *>(c); c += sz_long;
+    p->ws.sched = reinterpret_cast<uint32_t *>(c);
+    p->ws.sched_blocks = uint32_t(sched_blocks);
+    p->ws.max_long_lanes = uint32_t(long_lanes);
     p->ws.max_n = max_n;
-    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+    // Streams only where needed: each stream may take one of the process's few hardware
+    // queues, and streams sharing a queue wait behind each other's kernels.
+    e = hipSuccess;
+    if (flags & HB_PLAN_GRAPH) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && p->long_on) {
+        if ((e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming)) == hipSuccess)
+            e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
         hb_plan_destroy(p);
         return hip_error(e, "hb_plan_create: stream/event");
     }
@@ -678,6 +939,7 @@ int hb_plan_run(hb_plan *p, const uint8_t *algos, int algo, const uint8_t *messa
     d.stride = algos ? 32u : uint32_t(digest_size(algo));
     d.algo = algos ? 0 : algo;
     d.sort = (p->flags & HB_PLAN_NO_SORT) ? 0 : 1;
+    d.long_min_key = (p->long_on && d.sort) ? p->long_min_key : 0;
     if ((p->flags & HB_PLAN_AUTOTUNE) && !p->tuned) {
         d.mpl = p->mpl;
         const int mask = algos ? 7 : (1 << algo);
@@ -701,7 +963,8 @@ int hb_plan_config(const hb_plan *p, int *waves_per_cu, int *msgs_per_lane, int 
 int hb_plan_set_config(hb_plan *p, int waves_per_cu, int msgs_per_lane, int variant)
 {
     if (!p) return set_error(HB_EINVAL, "hb_plan_set_config: null plan");
-    if (waves_per_cu < 0 || waves_per_cu > 64 || msgs_per_lane < 0 || msgs_per_lane > kMaxMpl || variant < 0)
+    if (waves_per_cu < 0 || waves_per_cu > 64 || msgs_per_lane < 0 || msgs_per_lane > kMaxMpl || variant < 0 ||
+        variant > 1)
         return set_error(HB_EINVAL, "hb_plan_set_config: out of range");
     if (waves_per_cu) p->waves_per_cu = waves_per_cu;
     if (msgs_per_lane) p->mpl = msgs_per_lane;
@@ -731,6 +994,9 @@ void hb_plan_destroy(hb_plan *p)
     collect_timing(p, true);
     for (auto &e : p->ev_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    if (p->side) hipStreamDestroy(p->side);
+    if (p->ev_fork) hipEventDestroy(p->ev_fork);
+    if (p->ev_join) hipEventDestroy(p->ev_join);
     if (p->alloc) hipFree(p->alloc);
     delete p;
 }

@@ -19,6 +19,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -35,7 +36,10 @@
 namespace hb {
 namespace {
 
-constexpr int kStreams = 3;                    // compute streams (steps in flight)
+constexpr int kStreams = 2;                    // compute streams (steps in flight)
+constexpr size_t kMinBatch = 8;                // a step waits for this many staged requests...
+constexpr double kMaxWait = 200e-6;            // ...or for its oldest request to wait this long (s),
+                                               // unless no step is running
 constexpr uint64_t kMaxStepN = 1ull << 20;     // messages per device step
 constexpr int kStagers = 4;                    // staging threads
 constexpr uint64_t kPiece = 16ull << 20;       // staging copy granularity (per buffer half)
@@ -55,6 +59,7 @@ struct Req {
     St st = St::Pending;
     int status = HB_OK;
     double t_submit = 0, t_admit = 0, t_h2d = 0, t_done = 0;
+    double t_staged = 0;            // host time its copies were enqueued
     hipEvent_t copied = nullptr;    // last staging copy of this request
     bool stalled = false;           // was held back at the head of the queue
 };
@@ -67,10 +72,9 @@ struct Step {
     hipEvent_t done = nullptr;
 };
 
-// A staging thread's pinned double buffer and copy stream.
+// A staging thread's pinned double buffer (copies go on the server's one copy stream).
 struct Stager {
     std::thread thr;
-    hipStream_t stream = nullptr;
     uint8_t *buf = nullptr;          // 2 * kPiece pinned bytes
     hipEvent_t half_free[2] = {nullptr, nullptr};
     bool half_used[2] = {false, false};
@@ -103,7 +107,7 @@ struct hb_server {
     Arena arena;
     uint8_t *d_arena = nullptr;
     std::vector<hipEvent_t> ev_pool;
-    hipStream_t copy_in = nullptr;  // reference-event stream
+    hipStream_t copy_in = nullptr;  // all staging copies (one hardware queue for the copies)
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams] = {};
     uint8_t *h_meta[kStreams] = {}; // pinned: offsets | lengths | ids | digests
@@ -167,14 +171,14 @@ int stage_one(hb_server *s, Stager &g, int &half, Req *r)
             within += take;
             if (within == L) { ++i; within = 0; }
         }
-        hipError_t e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, g.stream);
-        if (e == hipSuccess) e = hipEventRecord(g.half_free[h], g.stream);
+        hipError_t e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, s->copy_in);
+        if (e == hipSuccess) e = hipEventRecord(g.half_free[h], s->copy_in);
         if (e != hipSuccess) return hip_error(e, "hb_server: staging copy");
         g.half_used[h] = true;
         dst += filled;
     }
     hipError_t e = hipEventCreate(&r->copied);
-    if (e == hipSuccess) e = hipEventRecord(r->copied, g.stream);
+    if (e == hipSuccess) e = hipEventRecord(r->copied, s->copy_in);
     if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
     return HB_OK;
 }
@@ -199,6 +203,7 @@ void stager_loop(hb_server *s, int w)
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (rc != HB_OK) r->status = rc;
+            r->t_staged = s->now();
             s->staged.push_back(r);
             s->staging_inflight--;
         }
@@ -345,7 +350,10 @@ void loop(hb_server *s)
                 s->stalls++;
             }
             if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
-            have_staged = !s->staged.empty();
+            // continuous batching: a step is launched when a stream is idle and either no
+            // step is running, enough requests are staged, or the oldest has waited long enough
+            have_staged = !s->staged.empty() &&
+                          (!any_busy || s->staged.size() >= kMinBatch || s->now() - s->staged.front()->t_staged >= kMaxWait);
         }
         if (admitted) s->cv_stage.notify_all();
         // 2. launch a step on a free compute stream
@@ -409,17 +417,19 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     for (Stager &g : s->stager) {
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&g.buf), 2 * kPiece, hipHostMallocDefault)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned staging", hipSuccess);
-        if ((e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&g.half_free[0], hipEventDisableTiming)) != hipSuccess ||
+        if ((e = hipEventCreateWithFlags(&g.half_free[0], hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&g.half_free[1], hipEventDisableTiming)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: staging stream", e);
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
+    // plans of the device steps: eager launches by default (HB_SERVER_PLAN_FLAGS overrides)
+    int plan_flags = 0;
+    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags = std::atoi(v);
     for (int k = 0; k < kStreams; ++k) {
         if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: stream", e);
-        int rc = hb_plan_create(&s->plan[k], kMaxStepN, 0);
+        int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags);
         if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN), hipHostMallocDefault)) !=
             hipSuccess)
@@ -549,10 +559,6 @@ void hb_server_destroy(hb_server *s)
     s->cv_stage.notify_all();
     for (Stager &g : s->stager) {
         if (g.thr.joinable()) g.thr.join();
-        if (g.stream) {
-            hipStreamSynchronize(g.stream);
-            hipStreamDestroy(g.stream);
-        }
         for (hipEvent_t e : g.half_free)
             if (e) hipEventDestroy(e);
         if (g.buf) hipHostFree(g.buf);

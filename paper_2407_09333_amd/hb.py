@@ -20,7 +20,7 @@ LIB_PATH = PKG / "libhb.so"
 HEADER = PKG.parent / "include" / "hb.h"
 
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_EHIP, HB_EBUDGET, HB_EBUSY = 0, -1, -2, -3, -4, -5
-PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT = 1, 2, 4
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT, PLAN_NO_LONG = 1, 2, 4, 8
 ALGO_IDS = {"md5": MD5, "sha1": SHA1, "sm3": SM3}
 
 _vp = ctypes.c_void_p
@@ -53,6 +53,7 @@ def lib() -> ctypes.CDLL:
         L.hash_batch_strided.argtypes = [_i, _vp, _vp, _vp, _u64, _vp, _u64, _vp]
         L.hash_batch_fixed.argtypes = [_i, _vp, _u64, _u64, _vp, _vp]
         L.hash_batch_mixed.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, _vp]
+        L.hash_digits9.argtypes = [_i, _u64, _u64, _vp, _vp]
         if hasattr(L, "hb_plan_create"):
             L.hb_plan_create.argtypes = [ctypes.POINTER(_vp), _u64, _i]
             L.hb_plan_run.argtypes = [_vp, _vp, _i, _vp, _vp, _vp, _u64, _vp, _vp]
@@ -190,6 +191,17 @@ def hash_batch_mixed(algos, messages, offsets, lengths, out=None, stream=None):
         out = torch.empty((n, 32), dtype=torch.uint8, device=msgs.device)
     check(lib().hash_batch_mixed(_ptr(al), _ptr(msgs), _ptr(offs), _ptr(lens), n, _ptr(out),
                                  _stream_ptr(stream)))
+    return out
+
+
+def hash_digits9(algo, start: int, n: int, out=None, stream=None):
+    """Digests of the 9-digit decimal strings of start .. start + n - 1 (generated on the
+    device); returns an (n, digest) uint8 CUDA tensor."""
+    torch = _torch()
+    a = algo_id(algo)
+    if out is None:
+        out = torch.empty((n, DIGEST_SIZE.get(a, 32)), dtype=torch.uint8, device="cuda")
+    check(lib().hash_digits9(a, start, n, _ptr(out), _stream_ptr(stream)))
     return out
 
 

@@ -66,3 +66,10 @@ def test_last_error_is_thread_local(L):
     t.join()
     assert seen["msg"] == ""
     assert "algorithm" in hb.last_error()
+
+
+def test_digits9_range_checked_before_launch(L):
+    assert L.hash_digits9(0, 999_999_999, 2, 64, None) == hb.HB_EINVAL
+    assert L.hash_digits9(0, 1_000_000_000, 1, 64, None) == hb.HB_EINVAL
+    assert L.hash_digits9(5, 0, 10, 64, None) == hb.HB_EINVAL
+    assert L.hash_digits9(1, 0, 0, None, None) == hb.HB_OK

@@ -60,13 +60,14 @@ def test_plan_mixed_with_long_empty_and_invalid(hb, flags):
     plan.close()
 
 
-@pytest.mark.parametrize("wpc,mpl", [(4, 1), (8, 2), (16, 4), (32, 1), (64, 3)])
-def test_launch_choices_give_identical_digests(hb, wpc, mpl):
+@pytest.mark.parametrize("wpc,mpl,var", [(4, 1, 0), (8, 2, 1), (16, 4, 0), (32, 1, 1), (64, 3, 1), (16, 2, 1)])
+def test_launch_choices_give_identical_digests(hb, wpc, mpl, var):
     msgs, offs, lens, algos = _batch_mixed_with_long(seed=7, total=1_000_000)
-    print(f"case choices wpc={wpc} mpl={mpl}", flush=True)
+    print(f"case choices wpc={wpc} mpl={mpl} variant={var}", flush=True)
     plan = hb.Plan(offs.size, flags=0)
-    plan.set_config(waves_per_cu=wpc, msgs_per_lane=mpl)
-    assert plan.config()["waves_per_cu"] == wpc and plan.config()["msgs_per_lane"] == mpl
+    plan.set_config(waves_per_cu=wpc, msgs_per_lane=mpl, variant=var)
+    cfg = plan.config()
+    assert cfg["waves_per_cu"] == wpc and cfg["msgs_per_lane"] == mpl and cfg["variant"] == var
     got = plan.run(msgs, offs, lens, algos=algos).cpu().numpy()
     assert_same(got, oracle.hash_batch(algos, msgs, offs, lens), f"wpc={wpc} mpl={mpl}")
     assert plan.kernel_ms() > 0
@@ -79,7 +80,7 @@ def test_autotune_picks_a_valid_choice(hb):
     plan = hb.Plan(30_000, flags=hb.PLAN_GRAPH | hb.PLAN_AUTOTUNE)
     got = plan.run(b.messages, b.offsets, b.lengths, algo=2).cpu().numpy()
     cfg = plan.config()
-    assert cfg["waves_per_cu"] in (8, 16, 32) and cfg["msgs_per_lane"] in (1, 2)
+    assert cfg["waves_per_cu"] in (8, 16, 32) and cfg["msgs_per_lane"] in (1, 2) and cfg["variant"] in (0, 1)
     assert_same(got, oracle.hash_batch(2, b.messages, b.offsets, b.lengths), "autotuned")
     plan.close()
 
@@ -178,3 +179,30 @@ def _check_sampled(hb, b, idx, got, algo):
     a = algo[idx] if isinstance(algo, np.ndarray) else algo
     want = oracle.hash_batch(a, host, noffs, lens, out_stride=got.shape[1])
     assert_same(got[torch.from_numpy(idx).cuda()].cpu().numpy(), want, "sampled full size")
+
+
+@pytest.mark.parametrize("scratch_mb,min_blocks", [("1", "256"), ("64", "2"), ("256", "16")])
+def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
+    """Messages above the block threshold run as rounds-only chains from precomputed
+    schedule words; with a tiny scratch only some of them fit and the rest take the
+    ordinary path.  Every digest must match the oracle either way."""
+    monkeypatch.setenv("HB_LONG_SCRATCH_MB", scratch_mb)
+    monkeypatch.setenv("HB_LONG_MIN_BLOCKS", min_blocks)
+    rng = np.random.default_rng(int(min_blocks))
+    n = 3000
+    lens = rng.integers(0, 40_000, size=n).astype(np.uint64)
+    lens[:40] = rng.integers(100_000, 300_000, size=40)  # some very long ones
+    lens[40:50] = [0, 1, 55, 56, 63, 64, 119, 120, 16_384, 16_383]
+    offs = workloads.packed(lens)
+    msgs = workloads.host_random_bytes(int(lens.sum()), seed=int(min_blocks) + 1)
+    algos = rng.integers(0, 3, size=n).astype(np.uint8)
+    print(f"case long path scratch={scratch_mb} min_blocks={min_blocks}", flush=True)
+    want = oracle.hash_batch(algos, msgs, offs, lens)
+    for flags in (hb.PLAN_GRAPH, 0):
+        plan = hb.Plan(n, flags=flags)
+        got = plan.run(msgs, offs, lens, algos=algos).cpu().numpy()
+        assert_same(got, want, f"long path flags={flags}")
+        plan.close()
+    plan = hb.Plan(n, flags=hb.PLAN_NO_LONG)
+    assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "no long path")
+    plan.close()
