@@ -133,8 +133,12 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags);
  * nb = floor((L + 8) / 64) + 1; counting sort by (algorithm, nb) descending; work items
  * of one wave each (algorithm-uniform lanes of near-equal nb); items merged by estimated
  * cost, longest first; one persistent launch whose waves pull items from an atomic queue.
- * Calls on one plan are serialised by the caller (a plan is not thread-safe); the host
- * waits for the previous run's parameter block to be consumed before reusing it.
+ * Messages of at least HB_LONG_MIN_BLOCKS blocks take the long-chain path (see
+ * hb_plan_create).  Per-run pointers and sizes reach the device through a one-thread
+ * kernel launched ahead of the pipeline with them as arguments, so a captured graph is
+ * replayed unchanged and consecutive runs need no host synchronisation.  Calls on one plan
+ * must be serialised by the caller (a plan is not thread-safe) and one plan's runs must
+ * share a stream, since they share the plan's workspace.
  */
 int hb_plan_run(hb_plan *plan, const uint8_t *algos, int algo, const uint8_t *messages,
                 const uint64_t *offsets, const uint64_t *lengths, uint64_t n,

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hb.h"
@@ -55,6 +56,14 @@ struct HostPipe {
         if (back) hipStreamDestroy(back);
     }
 
+    void release_streams()
+    {
+        if (compute) { hipStreamSynchronize(compute); hipStreamDestroy(compute); compute = nullptr; }
+        if (copy) { hipStreamSynchronize(copy); hipStreamDestroy(copy); copy = nullptr; }
+        if (back) { hipStreamSynchronize(back); hipStreamDestroy(back); back = nullptr; }
+        if (plan) { hb_plan_destroy(plan); plan = nullptr; plan_n = 0; }
+    }
+
     static void release(Slot &s)
     {
         if (s.h_msgs) hipHostFree(s.h_msgs);
@@ -70,6 +79,26 @@ struct HostPipe {
 thread_local std::unique_ptr<HostPipe> t_pipe;
 
 uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// memcpy split over up to 8 threads for large copies into pinned staging.
+void copy_parallel(uint8_t *dst, const uint8_t *src, uint64_t n)
+{
+    constexpr uint64_t kPer = 8ull << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint64_t parts = std::min<uint64_t>({(n + kPer - 1) / kPer, 8, hw});
+    if (parts <= 1) {
+        std::memcpy(dst, src, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const uint64_t step = (n + parts - 1) / parts;
+    for (uint64_t k = 1; k < parts; ++k) {
+        const uint64_t a = k * step, b = std::min(n, a + step);
+        if (a < b) th.emplace_back([=] { std::memcpy(dst + a, src + a, b - a); });
+    }
+    std::memcpy(dst, src, std::min(n, step));
+    for (auto &t : th) t.join();
+}
 
 // Make sure slot s holds at least `bytes` of payload and `n` messages.
 int ensure_slot(Slot &s, uint64_t bytes, uint64_t n)
@@ -134,6 +163,8 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
     if (!t_pipe || t_pipe->device != dev) {
         t_pipe.reset(new HostPipe());
         t_pipe->device = dev;
+    }
+    if (!t_pipe->copy) {
         if ((e = hipStreamCreateWithFlags(&t_pipe->copy, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipStreamCreateWithFlags(&t_pipe->compute, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipStreamCreateWithFlags(&t_pipe->back, hipStreamNonBlocking)) != hipSuccess) {
@@ -164,7 +195,7 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
     if (!P.plan || P.plan_n < largest_n) {
         if (P.plan) hb_plan_destroy(P.plan);
         P.plan = nullptr;
-        int rc = hb_plan_create(&P.plan, std::max<uint64_t>(largest_n, 4096), HB_PLAN_GRAPH);
+        int rc = hb_plan_create(&P.plan, std::max<uint64_t>(largest_n, 4096), 0);
         if (rc != HB_OK) return rc;
         P.plan_n = std::max<uint64_t>(largest_n, 4096);
     }
@@ -192,13 +223,21 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         if (rc != HB_OK) break;
         const uint64_t i0 = cuts[c], i1 = cuts[c + 1], cnt = i1 - i0;
         uint64_t pos = 0;
+        // a run of back-to-back messages is copied as one range
+        bool packed = true;
         for (uint64_t i = i0; i < i1; ++i) {
             const uint64_t L = lengths_host[i];
-            if (L) std::memcpy(s.h_msgs + pos, messages_host + offsets_host[i], L);
+            if (i > i0 && offsets_host[i] != offsets_host[i - 1] + lengths_host[i - 1]) packed = false;
             s.h_offs[i - i0] = pos;
             s.h_lens[i - i0] = L;
             if (algos_host) s.h_ids[i - i0] = algos_host[i];
             pos += L;
+        }
+        if (packed) {
+            if (pos) copy_parallel(s.h_msgs, messages_host + offsets_host[i0], pos);
+        } else {
+            for (uint64_t i = i0; i < i1; ++i)
+                if (lengths_host[i]) std::memcpy(s.h_msgs + s.h_offs[i - i0], messages_host + offsets_host[i], lengths_host[i]);
         }
         const uint64_t bytes = pos;
         if (bytes) e = hipMemcpyAsync(s.d_msgs, s.h_msgs, bytes, hipMemcpyHostToDevice, P.copy);
@@ -224,5 +263,9 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         int r2 = drain(s);
         if (rc == HB_OK) rc = r2;
     }
+    // Release the streams (and the plan's) between calls: each stream may hold one of the
+    // process's few hardware queues, and idle streams still shift which queue later streams
+    // of the caller (or of a serving loop) share.  Buffers are kept.
+    P.release_streams();
     return rc;
 }

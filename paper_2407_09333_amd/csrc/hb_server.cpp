@@ -423,8 +423,10 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
-    // plans of the device steps: eager launches by default (HB_SERVER_PLAN_FLAGS overrides)
-    int plan_flags = 0;
+    // Plans of the device steps: eager launches, no separate long-chain stream (a step's
+    // bulk is small, and every extra stream can end up sharing a hardware queue with the
+    // copy stream); HB_SERVER_PLAN_FLAGS overrides.
+    int plan_flags = HB_PLAN_NO_LONG;
     if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags = std::atoi(v);
     for (int k = 0; k < kStreams; ++k) {
         if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
