@@ -116,7 +116,7 @@ enum {
  * hb_plan_create -- reserve device workspace for batches of up to max_n messages and
  * build the launch plan.  The plan owns its workspace (about 4 bytes per message, a fixed
  * part of about 0.6 MB, and -- unless HB_PLAN_NO_LONG -- a long-chain scratch of
- * HB_LONG_SCRATCH_MB MiB, default 256) and, with HB_PLAN_GRAPH, a hipGraph captured on
+ * HB_LONG_SCRATCH_MB MiB, default 1024) and, with HB_PLAN_GRAPH, a hipGraph captured on
  * first run.  Long-chain path: messages of at least HB_LONG_MIN_BLOCKS blocks (default 256,
  * i.e. about 16 KiB) have every block's schedule words computed block-parallel first, then
  * run as rounds-only chains in a high-priority kernel beside the bulk kernel (a message's

@@ -173,32 +173,54 @@ template <int A> __device__ __forceinline__ void rounds(uint32_t s[8], const uin
     else sm3_rounds(s, ww);
 }
 
-// Load one block's precomputed words (kN of them, 16-byte aligned in scratch).
-template <int A> __device__ __forceinline__ void load_sched(const uint32_t *src, uint32_t *ww)
+// Scratch layout, wave-interleaved so each load instruction of a wave reads one
+// contiguous KiB: a long-chain wave owns a region of (its longest message's block count)
+// "wave-blocks"; in it, word group k (4 words) of block b of lane l sits at words
+// ((b * kGroups + k) * 64 + l) * 4.
+constexpr int kGroups = kSchedWords / 4;
+constexpr uint64_t kWaveBlockWords = uint64_t(kGroups) * 64 * 4;  // 32 KiB
+
+__device__ __forceinline__ uint64_t sched_at(uint64_t b, int k, uint32_t lane)
 {
-    const HB_GLOBAL u32x4 *q = reinterpret_cast<const HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(src));
+    return ((b * kGroups + uint64_t(k)) * 64u + lane) * 4u;
+}
+
+// Load block b's precomputed words (kN of them) of lane `lane` from wave region wr.
+template <int A> __device__ __forceinline__ void load_sched(const uint32_t *wr, uint64_t b, uint32_t lane, uint32_t *ww)
+{
+    const HB_GLOBAL uint32_t *q = reinterpret_cast<const HB_GLOBAL uint32_t *>(reinterpret_cast<uintptr_t>(wr));
 #pragma unroll
     for (int k = 0; k < SchedWords<A>::kN / 4; ++k) {
-        u32x4 v = q[k];
+        u32x4 v = *reinterpret_cast<const HB_GLOBAL u32x4 *>(q + sched_at(b, k, lane));
         ww[4 * k + 0] = v.x; ww[4 * k + 1] = v.y; ww[4 * k + 2] = v.z; ww[4 * k + 3] = v.w;
     }
 }
 
-// The chain of a message of nb blocks whose words are at sched + blk * kSchedWords: rounds
-// only, with the next block's words loaded while the current block is compressed (two
+// Store block b's words for lane `lane` into wave region wr.
+template <int A> __device__ __forceinline__ void store_sched(uint32_t *wr, uint64_t b, uint32_t lane, const uint32_t *ww)
+{
+    HB_GLOBAL uint32_t *q = reinterpret_cast<HB_GLOBAL uint32_t *>(reinterpret_cast<uintptr_t>(wr));
+#pragma unroll
+    for (int k = 0; k < SchedWords<A>::kN / 4; ++k)
+        *reinterpret_cast<HB_GLOBAL u32x4 *>(q + sched_at(b, k, lane)) =
+            u32x4{ww[4 * k + 0], ww[4 * k + 1], ww[4 * k + 2], ww[4 * k + 3]};
+}
+
+// The chain of a message of nb blocks whose words are in wave region wr, lane `lane`:
+// rounds only, the next block's words loaded while the current block is compressed (two
 // buffers, loop unrolled by two so no copies are needed).
 template <int A>
-__device__ __forceinline__ void chain_from_sched(const uint32_t *sched, uint64_t nb, uint32_t s[8])
+__device__ __forceinline__ void chain_from_sched(const uint32_t *wr, uint32_t lane, uint64_t nb, uint32_t s[8])
 {
     constexpr int N = SchedWords<A>::kN;
     uint32_t w0[N], w1[N];
     init_state<A>(s);
-    load_sched<A>(sched, w0);
+    load_sched<A>(wr, 0, lane, w0);
     uint64_t blk = 0;
     for (; blk + 2 <= nb; blk += 2) {
-        load_sched<A>(sched + (blk + 1) * kSchedWords, w1);
+        load_sched<A>(wr, blk + 1, lane, w1);
         rounds<A>(s, w0);
-        if (blk + 2 < nb) load_sched<A>(sched + (blk + 2) * kSchedWords, w0);
+        if (blk + 2 < nb) load_sched<A>(wr, blk + 2, lane, w0);
         rounds<A>(s, w1);
     }
     if (blk < nb) rounds<A>(s, w0);

@@ -62,7 +62,7 @@ struct PlanMeta {
     unsigned long long total_cost;
     uint32_t long_n[3];       // long-chain messages per algorithm (a prefix of its segment)
     uint32_t long_first[4];   // first long-lane index of each algorithm (padded to 64 lanes)
-    uint32_t long_blocks;     // scratch blocks in use
+    uint32_t long_blocks;     // scratch wave-blocks in use
     uint32_t max_key;         // largest key present (scans stop there)
 };
 
@@ -75,10 +75,10 @@ struct PlanWs {
     uint32_t *bin_start;      // 3 * kBins first sorted position of each key
     uint32_t *sorted;         // message indices, per-algorithm segments, padded to items
     uint32_t *order;          // item ids, longest first
-    uint32_t *long_base;      // per long lane: first scratch block of its message
-    uint32_t *sched;          // scratch: kSchedWords words per block of long messages
-    uint32_t sched_blocks;    // scratch capacity in blocks
-    uint32_t max_long_lanes;  // capacity of long_base
+    uint32_t *wave_base;      // per long-chain wave: first wave-block of its scratch region
+    uint32_t *sched;          // scratch: kWaveBlockWords words per wave-block
+    uint32_t sched_blocks;    // scratch capacity in wave-blocks
+    uint32_t max_long_waves;  // capacity of wave_base (one more entry holds the end)
     uint64_t max_n;
 };
 
@@ -352,16 +352,17 @@ __global__ __launch_bounds__(kThreads) void k_zero_invalid(PlanWs ws)
 }
 
 // Choose the long-chain messages: within each algorithm's segment, the leading messages
-// (longest first) whose key reaches long_min_key, while their blocks fit the scratch;
-// assign each its first scratch block.  One workgroup; lanes padded to 64 per algorithm
-// so each long-chain wave is algorithm-uniform.
+// (longest first) whose key reaches long_min_key, taken a wave (64 messages) at a time
+// while the waves' scratch regions fit; a wave's region is as many wave-blocks as its
+// first (longest) message has blocks.  One workgroup; each long-chain wave is
+// algorithm-uniform.
 __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
 {
     __shared__ uint32_t part[kScanThreads];
-    __shared__ uint32_t s_run, s_lane, s_stop;
+    __shared__ uint32_t s_run, s_wave, s_stop;
     const PlanDesc d = *ws.desc;
     PlanMeta *m = ws.meta;
-    if (threadIdx.x == 0) { s_run = 0; s_lane = 0; }
+    if (threadIdx.x == 0) { s_run = 0; s_wave = 0; }
     __syncthreads();
     for (int o = 0; o < 3; ++o) {
         const int a = long_order(o);
@@ -380,20 +381,20 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
             cand = part[0];
             __syncthreads();
         }
-        const uint32_t lane0 = s_lane;
-        const uint32_t lane_cap = ws.max_long_lanes;
+        const uint32_t nw = (cand + 63u) / 64u;
+        const uint32_t w0 = s_wave;
         if (threadIdx.x == 0) s_stop = 0;
         __syncthreads();
         uint32_t taken = 0;
-        for (uint32_t c0 = 0; c0 < cand; c0 += kScanThreads) {
+        for (uint32_t c0 = 0; c0 < nw; c0 += kScanThreads) {
             if (s_stop) break;
-            const uint32_t i = c0 + threadIdx.x;
-            uint32_t nb = 0;
-            if (i < cand) {
-                const uint32_t idx = ws.sorted[m->seg_pos[a] + i];
-                nb = uint32_t((d.lens[idx] + 8u) / 64u + 1u);
+            const uint32_t wi = c0 + threadIdx.x;
+            uint32_t cost = 0;
+            if (wi < nw) {
+                const uint32_t idx = ws.sorted[m->seg_pos[a] + wi * 64u];
+                cost = uint32_t((d.lens[idx] + 8u) / 64u + 1u);
             }
-            part[threadIdx.x] = nb;
+            part[threadIdx.x] = cost;
             __syncthreads();
             for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
                 const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
@@ -401,9 +402,9 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
                 part[threadIdx.x] += v;
                 __syncthreads();
             }
-            const uint64_t base = uint64_t(s_run) + part[threadIdx.x] - nb;
-            const bool fits = i < cand && base + nb <= ws.sched_blocks && lane0 + i + 64 * (3 - o) < lane_cap;
-            if (fits) ws.long_base[lane0 + i] = uint32_t(base);
+            const uint64_t base = uint64_t(s_run) + part[threadIdx.x] - cost;
+            const bool fits = wi < nw && base + cost <= ws.sched_blocks && w0 + wi < ws.max_long_waves;
+            if (fits) ws.wave_base[w0 + wi] = uint32_t(base);
             const uint32_t nfit = uint32_t(__syncthreads_count(fits));
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -413,18 +414,16 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
             taken += nfit;
             __syncthreads();
         }
-        const uint32_t padded = (taken + 63u) / 64u * 64u;
-        for (uint32_t i = taken + threadIdx.x; i < padded; i += kScanThreads) ws.long_base[lane0 + i] = s_run;
-        __syncthreads();
         if (threadIdx.x == 0) {
-            m->long_n[a] = taken;
-            m->long_first[a] = lane0;
-            s_lane = lane0 + padded;
+            m->long_n[a] = min(cand, taken * 64u);
+            m->long_first[a] = w0 * 64u;
+            s_wave = w0 + taken;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        m->long_first[3] = s_lane;  // end of the long lanes (not indexed by algorithm)
+        ws.wave_base[s_wave] = s_run;  // end of the last region
+        m->long_first[3] = s_wave * 64u;
         m->long_blocks = s_run;
     }
 }
@@ -444,38 +443,39 @@ __device__ __forceinline__ int long_algo(const PlanMeta &m, uint32_t g, uint32_t
     return MD5;
 }
 
-// Schedule words of every block of every long-chain message: one lane per block.
+// Schedule words of every block of every long-chain message: one lane per (wave-block,
+// lane of that wave), so each store instruction of a wave writes one contiguous KiB.
 __global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
 {
     const PlanDesc d = *ws.desc;
     const PlanMeta m = *ws.meta;
-    const uint32_t total = m.long_blocks, lanes = m.long_first[3];
-    for (uint32_t gb = blockIdx.x * kThreads + threadIdx.x; gb < total; gb += gridDim.x * kThreads) {
-        // last long lane whose first block is <= gb (padding lanes repeat the next base)
-        uint32_t lo = 0, hi = lanes;
+    const uint32_t nwaves = m.long_first[3] / 64u;
+    const uint64_t total = uint64_t(m.long_blocks) * 64u;
+    for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < total; t += uint64_t(gridDim.x) * kThreads) {
+        const uint32_t gb = uint32_t(t / 64u), l = uint32_t(t % 64u);
+        // the wave whose region holds wave-block gb
+        uint32_t lo = 0, hi = nwaves;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) / 2;
-            if (ws.long_base[mid] <= gb) lo = mid;
+            if (ws.wave_base[mid] <= gb) lo = mid;
             else hi = mid;
         }
         uint32_t i = 0;
-        const int a = long_algo(m, lo, i);
-        if (i >= m.long_n[a]) continue;  // a padding lane: cannot be the last lane at or below gb
+        const int a = long_algo(m, lo * 64u + l, i);
+        if (i >= m.long_n[a]) continue;  // a padding lane
         const uint32_t idx = ws.sorted[m.seg_pos[a] + i];
         const uint64_t len = d.lens[idx];
-        const uint64_t nb = (len + 8u) / 64u + 1u, blk = gb - ws.long_base[lo];
-        if (blk >= nb) continue;
+        const uint64_t nb = (len + 8u) / 64u + 1u, blk = gb - ws.wave_base[lo];
+        if (blk >= nb) continue;  // shorter than the wave's longest message
+        uint32_t *wr = ws.sched + uint64_t(ws.wave_base[lo]) * kWaveBlockWords;
         uint32_t w[16], out[kSchedWords];
-        uint32_t *dst = ws.sched + uint64_t(gb) * kSchedWords;
-        HB_GLOBAL u32x4 *q = reinterpret_cast<HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(dst));
 #define HB_SCHED_CASE(A)                                                                          \
         {                                                                                         \
             const Msg mm = make_msg<A>(d.msgs + d.offs[idx], len);                                \
             if (blk < len / 64u) load_full_block(mm, blk, w);                                     \
             else load_any_block<Traits<A>::kBE>(mm, blk, blk + 1 == nb, w);                       \
             sched_block<A>(w, out);                                                               \
-            for (int k = 0; k < SchedWords<A>::kN / 4; ++k)                                       \
-                q[k] = u32x4{out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]};          \
+            store_sched<A>(wr, blk, l, out);                                                      \
         }
         if (a == MD5) HB_SCHED_CASE(MD5)
         else if (a == SHA1) HB_SCHED_CASE(SHA1)
@@ -505,10 +505,11 @@ __global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
     uint32_t st[8];
     uint8_t *out = d.out + uint64_t(idx) * d.stride;
     if constexpr (SCHED) {
-        const uint32_t *src = ws.sched + uint64_t(ws.long_base[g]) * kSchedWords;
-        if (a == MD5) { chain_from_sched<MD5>(src, nb, st); store_digest<MD5>(out, st, d.stride); }
-        else if (a == SHA1) { chain_from_sched<SHA1>(src, nb, st); store_digest<SHA1>(out, st, d.stride); }
-        else { chain_from_sched<SM3>(src, nb, st); store_digest<SM3>(out, st, d.stride); }
+        const uint32_t *wr = ws.sched + uint64_t(ws.wave_base[g / 64u]) * kWaveBlockWords;
+        const uint32_t l = g % 64u;
+        if (a == MD5) { chain_from_sched<MD5>(wr, l, nb, st); store_digest<MD5>(out, st, d.stride); }
+        else if (a == SHA1) { chain_from_sched<SHA1>(wr, l, nb, st); store_digest<SHA1>(out, st, d.stride); }
+        else { chain_from_sched<SM3>(wr, l, nb, st); store_digest<SM3>(out, st, d.stride); }
     } else {
         const uint8_t *msg = d.msgs + d.offs[idx];
         const uint64_t len = d.lens[idx];
@@ -726,7 +727,7 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         // fork: the long chains start first on the side stream and run beside the bulk
         hipEventRecord(p->ev_fork, s);
         hipStreamWaitEvent(p->side, p->ev_fork, 0);
-        const int long_blocks = int((ws.max_long_lanes + kThreads - 1) / kThreads);
+        const int long_blocks = int((uint64_t(ws.max_long_waves) * 64u + kThreads - 1) / kThreads);
         if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         hipEventRecord(p->ev_join, p->side);
@@ -869,20 +870,21 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     // long-chain scratch: HB_LONG_SCRATCH_MB (default 256) of precomputed block words for
     // messages of at least HB_LONG_MIN_BLOCKS (default 256) blocks
     p->long_on = !(flags & HB_PLAN_NO_LONG) && !(flags & HB_PLAN_NO_SORT);
-    uint64_t scratch_mb = 256, min_blocks = 256;
+    uint64_t scratch_mb = 1024, min_blocks = 256;
     if (const char *v = std::getenv("HB_LONG_SCRATCH_MB")) scratch_mb = std::strtoull(v, nullptr, 10);
     if (const char *v = std::getenv("HB_LONG_MIN_BLOCKS")) min_blocks = std::strtoull(v, nullptr, 10);
     if (scratch_mb == 0 || min_blocks < 2 || min_blocks >= kBins) p->long_on = false;
     if (const char *v = std::getenv("HB_LONG_MODE")) p->long_sched = std::strcmp(v, "direct") != 0;
-    uint64_t sched_blocks = 0, long_lanes = 0, scratch_blocks = 0;
+    uint64_t sched_blocks = 0, long_waves = 0, scratch_blocks = 0;
     if (p->long_on) {
-        // direct mode needs no scratch: the block budget only bounds how many lanes are long
-        sched_blocks = std::min<uint64_t>(scratch_mb * (1ull << 20) / (kSchedWords * 4), 0xffffffffull);
-        long_lanes = sched_blocks / min_blocks + 4 * 64;
+        // wave-blocks of scratch; direct mode allocates none (the budget then only bounds
+        // how many waves run as long chains)
+        sched_blocks = std::min<uint64_t>(scratch_mb * (1ull << 20) / (kWaveBlockWords * 4), 0xffffffffull);
+        long_waves = sched_blocks / min_blocks + 3;
         scratch_blocks = p->long_sched ? sched_blocks : 0;
         p->long_min_key = uint32_t(min_blocks);
     }
-    const uint64_t sz_long = up(long_lanes * 4), sz_sched = up(scratch_blocks * kSchedWords * 4);
+    const uint64_t sz_long = up((long_waves + 1) * 4), sz_sched = up(scratch_blocks * kWaveBlockWords * 4);
     const uint64_t total = sz_desc + sz_meta + 3 * sz_bins + sz_sorted + sz_order + sz_long + sz_sched;
     e = hipMalloc(&p->alloc, total);
     if (e != hipSuccess) { delete p; return set_error(HB_ENOMEM, "hb_plan_create: workspace allocation failed"); }
@@ -894,10 +896,10 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     p->ws.bin_start = reinterpret_cast<uint32_t *>(c); c += sz_bins;
     p->ws.sorted = reinterpret_cast<uint32_t *>(c); c += sz_sorted;
     p->ws.order = reinterpret_cast<uint32_t *>(c); c += sz_order;
-    p->ws.long_base = reinterpret_cast<uint32_t *>(c); c += sz_long;
+    p->ws.wave_base = reinterpret_cast<uint32_t *>(c); c += sz_long;
     p->ws.sched = reinterpret_cast<uint32_t *>(c);
     p->ws.sched_blocks = uint32_t(sched_blocks);
-    p->ws.max_long_lanes = uint32_t(long_lanes);
+    p->ws.max_long_waves = uint32_t(long_waves);
     p->ws.max_n = max_n;
     // Streams only where needed: each stream may take one of the process's few hardware
     // queues, and streams sharing a queue wait behind each other's kernels.

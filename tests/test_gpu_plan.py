@@ -181,7 +181,7 @@ def _check_sampled(hb, b, idx, got, algo):
     assert_same(got[torch.from_numpy(idx).cuda()].cpu().numpy(), want, "sampled full size")
 
 
-@pytest.mark.parametrize("scratch_mb,min_blocks", [("1", "256"), ("64", "2"), ("256", "16")])
+@pytest.mark.parametrize("scratch_mb,min_blocks", [("1", "256"), ("512", "2"), ("1024", "16")])
 def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
     """Messages above the block threshold run as rounds-only chains from precomputed
     schedule words; with a tiny scratch only some of them fit and the rest take the
