@@ -100,6 +100,41 @@ int hash_batch_mixed(const uint8_t *algos, const uint8_t *messages, const uint64
 int hash_digits9(int algo, uint64_t start, uint64_t n, uint8_t *digests_out, void *stream);
 
 /* ------------------------------------------------------------------------------------ */
+/* Incremental hashing: per-message chaining state between launches.                      */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * Chaining state of one message being hashed in pieces (the paper's single-message op and
+ * its multi-message form, Sec. IV-B, split over several launches).  h[] holds the chaining
+ * value words (MD5 4, SHA-1 5, SM3 8; the rest unused), bytes the number of message bytes
+ * absorbed so far, flags 1 if an update piece was not a whole number of 64-byte blocks.
+ * States live in device memory; they may be copied out and back in to suspend and resume.
+ */
+typedef struct hb_state {
+    uint32_t h[8];
+    uint64_t bytes;
+    uint64_t flags;
+} hb_state;
+
+/* Set n device states to the algorithm's initial value (RFC 1321 Sec. 3.3, FIPS 180-4
+ * Sec. 5.3.1, GB/T 32905 Sec. 4.1).  states: device, 8-byte aligned. */
+int hash_init_batch(int algo, hb_state *states, uint64_t n, void *stream);
+
+/* Absorb piece i (messages[offsets[i] .. + lengths[i]), device) into state i.  Pieces
+ * before the final one must be whole blocks: a length that is not a multiple of 64 marks
+ * the state invalid (flags = 1) and is not absorbed; an invalid state ignores later
+ * pieces.  Allocates nothing. */
+int hash_update_batch(int algo, hb_state *states, const uint8_t *messages, const uint64_t *offsets,
+                      const uint64_t *lengths, uint64_t n, void *stream);
+
+/* Absorb the last piece i (any length, possibly 0) and the padding, whose length field
+ * counts every byte absorbed by the state plus this piece; write digest i to digests_out
+ * (device, n x digest size, 4-byte aligned).  States are read only.  An invalid state
+ * gives an all-zero digest slot.  Allocates nothing. */
+int hash_final_batch(int algo, const hb_state *states, const uint8_t *messages, const uint64_t *offsets,
+                     const uint64_t *lengths, uint64_t n, uint8_t *digests_out, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
 /* Batched form: length-bucketed, longest-first, persistent fused launch in a hipGraph.  */
 /* ------------------------------------------------------------------------------------ */
 

@@ -241,6 +241,7 @@ template <int A> __device__ __forceinline__ void compress(uint32_t s[8], const u
 struct Msg {
     const HB_GLOBAL uint32_t *p;
     uint64_t len;
+    uint64_t bits;   // value of the padding's length field: 8 x (all bytes hashed so far + len)
     uint32_t r;
     uint32_t sel;
 };
@@ -252,6 +253,7 @@ template <int A> __device__ __forceinline__ Msg make_msg(const uint8_t *base, ui
     m.p = reinterpret_cast<const HB_GLOBAL uint32_t *>(a & ~uintptr_t(3));
     m.r = uint32_t(a & 3u);
     m.len = len;
+    m.bits = len << 3;
     m.sel = Traits<A>::kBE ? sel_be(m.r) : sel_le(m.r);
     return m;
 }
@@ -339,24 +341,22 @@ __device__ __forceinline__ void load_any_block(const Msg &m, uint64_t blk, bool 
         w[i] = (x & keep) | mark;
     }
     if (last) {
-        const uint64_t bits = m.len << 3;
+        const uint64_t bits = m.bits;
         const uint32_t lo = uint32_t(bits), hi = uint32_t(bits >> 32);
         w[14] = BE ? hi : lo;
         w[15] = BE ? lo : hi;
     }
 }
 
-// Digest of one message into s[0 .. kWords).  The floor(L / 64) whole message blocks
-// are read directly; the remaining one or two blocks of the nb = floor((L + 8) / 64) + 1
-// are assembled in registers.  When every lane of a wave has the same length the loop
-// and its branch are wave-uniform.
-template <int A>
-__device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, uint32_t s[8])
+// Absorb the piece m into the chaining value s: its floor(L / 64) whole blocks are read
+// directly; with PAD the remaining one or two blocks of nb = floor((L + 8) / 64) + 1 --
+// tail bytes, 0x80, zeros and the length field m.bits -- are assembled in registers.
+// When every lane of a wave has the same length the loop and its branch are wave-uniform.
+template <int A, bool PAD>
+__device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
 {
-    const Msg m = make_msg<A>(base, len);
-    const uint64_t nb = (len + 8u) / 64u + 1u;
-    const uint64_t nfast = len / 64u;
-    init_state<A>(s);
+    const uint64_t nfast = m.len / 64u;
+    const uint64_t nb = PAD ? (m.len + 8u) / 64u + 1u : nfast;
     uint64_t blk = 0;
     if constexpr (A == MD5) {
         // MD5 does the least work per byte, so it is the one HBM re-reads would bound:
@@ -375,6 +375,16 @@ __device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, 
         else load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
         compress<A>(s, w);
     }
+}
+
+// Digest state of one whole message: the initial value, then every block including the
+// padding.
+template <int A>
+__device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, uint32_t s[8])
+{
+    const Msg m = make_msg<A>(base, len);
+    init_state<A>(s);
+    absorb<A, true>(m, s);
 }
 
 // As hash_message, with the next whole block's loads issued before the current block is

@@ -54,6 +54,9 @@ def lib() -> ctypes.CDLL:
         L.hash_batch_fixed.argtypes = [_i, _vp, _u64, _u64, _vp, _vp]
         L.hash_batch_mixed.argtypes = [_vp, _vp, _vp, _vp, _u64, _vp, _vp]
         L.hash_digits9.argtypes = [_i, _u64, _u64, _vp, _vp]
+        L.hash_init_batch.argtypes = [_i, _vp, _u64, _vp]
+        L.hash_update_batch.argtypes = [_i, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.hash_final_batch.argtypes = [_i, _vp, _vp, _vp, _vp, _u64, _vp, _vp]
         if hasattr(L, "hb_plan_create"):
             L.hb_plan_create.argtypes = [ctypes.POINTER(_vp), _u64, _i]
             L.hb_plan_run.argtypes = [_vp, _vp, _i, _vp, _vp, _vp, _u64, _vp, _vp]
@@ -202,6 +205,38 @@ def hash_digits9(algo, start: int, n: int, out=None, stream=None):
     if out is None:
         out = torch.empty((n, DIGEST_SIZE.get(a, 32)), dtype=torch.uint8, device="cuda")
     check(lib().hash_digits9(a, start, n, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+STATE_BYTES = 48  # sizeof(hb_state): 8 chaining words, u64 byte count, u64 flags
+
+
+def hash_init(algo, n: int, stream=None):
+    """n chaining states (an (n, 6) int64 CUDA tensor, 48 bytes each) at the initial value."""
+    torch = _torch()
+    st = torch.empty((n, STATE_BYTES // 8), dtype=torch.int64, device="cuda")
+    check(lib().hash_init_batch(algo_id(algo), _ptr(st), n, _stream_ptr(stream)))
+    return st
+
+
+def hash_update(algo, states, messages, offsets, lengths, stream=None):
+    """Absorb whole-block pieces into the states (in place)."""
+    msgs, offs, lens = _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+    check(lib().hash_update_batch(algo_id(algo), _ptr(states), _ptr(msgs), _ptr(offs), _ptr(lens),
+                                  offs.numel(), _stream_ptr(stream)))
+    return states
+
+
+def hash_final(algo, states, messages, offsets, lengths, out=None, stream=None):
+    """Absorb the last pieces and the padding; returns (n, digest) digests."""
+    torch = _torch()
+    a = algo_id(algo)
+    msgs, offs, lens = _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+    n = offs.numel()
+    if out is None:
+        out = torch.empty((n, DIGEST_SIZE.get(a, 32)), dtype=torch.uint8, device="cuda")
+    check(lib().hash_final_batch(a, _ptr(states), _ptr(msgs), _ptr(offs), _ptr(lens), n, _ptr(out),
+                                 _stream_ptr(stream)))
     return out
 
 

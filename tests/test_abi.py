@@ -73,3 +73,15 @@ def test_digits9_range_checked_before_launch(L):
     assert L.hash_digits9(0, 1_000_000_000, 1, 64, None) == hb.HB_EINVAL
     assert L.hash_digits9(5, 0, 10, 64, None) == hb.HB_EINVAL
     assert L.hash_digits9(1, 0, 0, None, None) == hb.HB_OK
+
+
+def test_state_layout_and_stream_argument_checks(L):
+    import ctypes
+
+    assert hb.STATE_BYTES == 48
+    assert L.hash_init_batch(9, 64, 1, None) == hb.HB_EINVAL
+    assert L.hash_init_batch(0, None, 3, None) == hb.HB_EINVAL
+    assert L.hash_init_batch(0, 68, 3, None) == hb.HB_EINVAL  # not 8-byte aligned
+    assert L.hash_update_batch(1, 64, None, None, None, 2, None) == hb.HB_EINVAL
+    assert L.hash_final_batch(2, 64, 64, 64, 64, 2, 66, None) == hb.HB_EINVAL  # misaligned out
+    assert L.hash_final_batch(2, None, None, None, None, 0, None, None) == hb.HB_OK
