@@ -36,7 +36,9 @@
 namespace hb {
 namespace {
 
-constexpr int kStreams = 2;                    // compute streams (steps in flight)
+constexpr int kStreams = 2;                    // compute streams: 0 short requests, 1 long
+constexpr uint64_t kLongChain = 128 * 1350;    // a request is "long" if its longest message's
+                                               // chain exceeds this many ops (128 SM3 blocks)
 constexpr size_t kMinBatch = 8;                // a step waits for this many staged requests...
 constexpr double kMaxWait = 200e-6;            // ...or for its oldest request to wait this long (s),
                                                // unless no step is running
@@ -62,6 +64,7 @@ struct Req {
     double t_staged = 0;            // host time its copies were enqueued
     hipEvent_t copied = nullptr;    // last staging copy of this request
     bool stalled = false;           // was held back at the head of the queue
+    int cls = 0;                    // 0: short chains only, 1: has a long chain
 };
 
 struct Step {
@@ -98,7 +101,7 @@ struct hb_server {
     uint64_t next_ticket = 1;
     int slots_used = 0;
     std::deque<Req *> to_stage;     // admitted, waiting for a staging thread (under mu)
-    std::vector<Req *> staged;      // copies enqueued, waiting for a step (under mu)
+    std::vector<Req *> staged[2];   // copies enqueued, waiting for a step, by class (under mu)
     std::condition_variable cv_stage;
     Stager stager[kStagers];
     bool stop_stagers = false;
@@ -204,25 +207,28 @@ void stager_loop(hb_server *s, int w)
             std::lock_guard<std::mutex> lk(s->mu);
             if (rc != HB_OK) r->status = rc;
             r->t_staged = s->now();
-            s->staged.push_back(r);
+            s->staged[r->cls].push_back(r);
             s->staging_inflight--;
         }
         s->cv_work.notify_one();
     }
 }
 
-// Launch everything staged as one step on compute stream k.
-int launch_step(hb_server *s, int k)
+// Launch the staged requests of class c as one step on compute stream k.  Requests with
+// only short chains are batched apart from those holding a long one, so a short request
+// does not wait for another request's long chain to finish.
+int launch_step(hb_server *s, int k, int c)
 {
     auto st = std::make_unique<Step>();
     uint64_t n = 0;
     {
         std::lock_guard<std::mutex> g(s->mu);
+        std::vector<Req *> &q = s->staged[c];
         size_t take = 0;
-        while (take < s->staged.size() && n + s->staged[take]->n <= kMaxStepN) n += s->staged[take++]->n;
+        while (take < q.size() && n + q[take]->n <= kMaxStepN) n += q[take++]->n;
         if (take == 0) return HB_OK;
-        st->reqs.assign(s->staged.begin(), s->staged.begin() + take);
-        s->staged.erase(s->staged.begin(), s->staged.begin() + take);
+        st->reqs.assign(q.begin(), q.begin() + take);
+        q.erase(q.begin(), q.begin() + take);
     }
     st->n = n;
     st->algo = st->reqs[0]->algo;
@@ -315,17 +321,16 @@ void finish_step(hb_server *s, int k, int status)
 void loop(hb_server *s)
 {
     hipSetDevice(s->device);
-    int next_stream = 0;
     for (;;) {
         // 1. admission, in arrival order; admitted requests go to the staging threads
         size_t admitted = 0;
-        bool have_staged = false;
+        int launch_cls[kStreams] = {-1, -1};  // class to launch on each idle stream
         {
             std::unique_lock<std::mutex> g(s->mu);
             bool any_busy = false;
             for (auto &b : s->busy) any_busy |= bool(b);
-            if (s->pending.empty() && s->to_stage.empty() && s->staging_inflight == 0 && s->staged.empty() &&
-                !any_busy) {
+            if (s->pending.empty() && s->to_stage.empty() && s->staging_inflight == 0 && s->staged[0].empty() &&
+                s->staged[1].empty() && !any_busy) {
                 if (s->stop) break;
                 s->cv_work.wait_for(g, std::chrono::milliseconds(50));
                 continue;
@@ -350,27 +355,32 @@ void loop(hb_server *s)
                 s->stalls++;
             }
             if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
-            // continuous batching: a step is launched when a stream is idle and either no
-            // step is running, enough requests are staged, or the oldest has waited long enough
-            have_staged = !s->staged.empty() &&
-                          (!any_busy || s->staged.size() >= kMinBatch || s->now() - s->staged.front()->t_staged >= kMaxWait);
+            // continuous batching: stream k serves class k; a step is launched when its
+            // stream is idle and either no step is running, enough requests are staged, or
+            // the oldest has waited long enough.  An idle stream whose class has nothing
+            // staged takes the other class's requests while that class's stream is busy.
+            const double now = s->now();
+            auto ready = [&](int c) {
+                const std::vector<Req *> &q = s->staged[c];
+                return !q.empty() && (!any_busy || q.size() >= kMinBatch || now - q.front()->t_staged >= kMaxWait);
+            };
+            for (int k = 0; k < kStreams; ++k) {
+                if (s->busy[k]) continue;
+                if (ready(k)) launch_cls[k] = k;
+                else if (s->staged[k].empty() && s->busy[1 - k] && ready(1 - k)) launch_cls[k] = 1 - k;
+            }
+            if (launch_cls[0] >= 0 && launch_cls[0] == launch_cls[1]) launch_cls[1] = -1;
         }
         if (admitted) s->cv_stage.notify_all();
-        // 2. launch a step on a free compute stream
-        if (have_staged) {
-            for (int t = 0; t < kStreams; ++t) {
-                const int k = (next_stream + t) % kStreams;
-                if (!s->busy[k]) {
-                    int rc = launch_step(s, k);
-                    if (rc != HB_OK) {
-                        s->fatal = rc;
-                        if (s->busy[k]) {
-                            if (hipStreamSynchronize(s->compute[k]) != hipSuccess) rc = HB_EHIP;
-                            finish_step(s, k, rc);
-                        }
-                    }
-                    next_stream = (k + 1) % kStreams;
-                    break;
+        // 2. launch steps on idle compute streams
+        for (int k = 0; k < kStreams; ++k) {
+            if (launch_cls[k] < 0) continue;
+            int rc = launch_step(s, k, launch_cls[k]);
+            if (rc != HB_OK) {
+                s->fatal = rc;
+                if (s->busy[k]) {
+                    if (hipStreamSynchronize(s->compute[k]) != hipSuccess) rc = HB_EHIP;
+                    finish_step(s, k, rc);
                 }
             }
         }
@@ -461,11 +471,14 @@ int hb_server_submit(hb_server *s, int algo_or_mixed, const uint8_t *algos, cons
     if (n > kMaxStepN) return set_error(HB_EINVAL, "hb_server_submit: more than 2^20 messages in one request");
     if (!offsets || !lengths || !digests_out || (mixed && !algos))
         return set_error(HB_EINVAL, "hb_server_submit: null host pointer");
-    uint64_t payload = 0;
+    uint64_t payload = 0, chain = 0;
+    static constexpr uint64_t kOps[3] = {340, 620, 1350};  // VALU ops per block
     for (uint64_t i = 0; i < n; ++i) {
         if (lengths[i] >= (1ull << 61)) return set_error(HB_EINVAL, "hb_server_submit: length beyond 2^61");
         if (mixed && algos[i] > HB_SM3) return set_error(HB_EINVAL, "hb_server_submit: unknown algorithm id in algos");
         payload += lengths[i];
+        const uint64_t c = ((lengths[i] + 8) / 64 + 1) * kOps[mixed ? algos[i] : algo_or_mixed];
+        chain = c > chain ? c : chain;
     }
     if (payload && !messages) return set_error(HB_EINVAL, "hb_server_submit: null messages");
     if (Arena::round_up(payload) > s->arena.capacity())
@@ -479,6 +492,7 @@ int hb_server_submit(hb_server *s, int algo_or_mixed, const uint8_t *algos, cons
     r->n = n;
     r->out = digests_out;
     r->payload = payload;
+    r->cls = chain > kLongChain ? 1 : 0;
     r->t_submit = s->now();
     {
         std::lock_guard<std::mutex> g(s->mu);
