@@ -388,10 +388,17 @@ def bench_digits9(args):
     return res
 
 
-def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9)):
+# where a serving request's latency goes (from its trace), reported as [p50, p99] ms each:
+# wait for admission, wait for a staging thread, packing + copy enqueue, copy completion,
+# wait for a step launch, wait for the stream / metadata, the step's hashing and digest
+# copy, and host completion (digests to the caller, polling)
+SERVE_PARTS = ("admit_wait", "stager_wait", "pack", "copy", "batch_wait", "exec_wait", "exec", "complete")
+
+
+def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9), cap_burst=2048):
     """Open-loop Poisson arrivals; each request 1..10,000 messages (log-uniform count),
     algorithm uniform over the three, lengths log-normal (median 256 B, cap 64 KiB); device
-    budget 64 GiB.  Capacity C is measured first with a saturating burst; then requests
+    budget 64 GiB.  Capacity C is measured first with a saturating burst of 2,048 requests; then requests
     arrive at 0.5 C, 0.7 C (the headline) and 0.9 C; latency = completion time - scheduled
     arrival time (no coordinated omission)."""
     from paper_2407_09333_amd import hb, workloads
@@ -400,13 +407,19 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
     srv = hb.Server(hbm_budget_bytes=64 << 30, max_slots=1024)
     for r in pool[:16]:  # warm-up
         srv.wait(srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos))
+    # capacity: a saturating burst long enough (cap_burst requests, the pool cycled) that
+    # the pipeline's fill and drain are a small part of it
     t0 = srv.now()
-    ts = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in pool]
+    burst = [pool[k % pool_size] for k in range(cap_burst)]
+    ts = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in burst]
+    t_sub = srv.now() - t0
     for t in ts:
         srv.wait(t)
     t1 = max(srv.times(t)["done"] for t in ts)
-    cap_rps = len(pool) / (t1 - t0)
-    cap_bytes = sum(int(r.lengths.sum()) for r in pool) / (t1 - t0)
+    cap_rps = len(burst) / (t1 - t0)
+    cap_bytes = sum(int(r.lengths.sum()) for r in burst) / (t1 - t0)
+    print(f"bench: serving capacity {cap_rps:.0f} req/s ({cap_bytes / 1e9:.2f} GB/s), "
+          f"burst of {cap_burst} submitted in {t_sub * 1e3:.1f} ms", file=sys.stderr, flush=True)
     runs = []
     for frac in fractions:
         rate = frac * cap_rps
@@ -430,12 +443,17 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
             payload += int(r.lengths.sum())
         lat = np.zeros(n_req)
         phases = np.zeros((n_req, 3))
+        parts = np.zeros((n_req, len(SERVE_PARTS)))
         done_max = 0.0
         for k, t in enumerate(tickets):
             srv.wait(t)
-            tm = srv.times(t)
+            tm = srv.trace(t)
             lat[k] = tm["done"] - sched[k]
             phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
+            parts[k] = (tm["admit"] - sched[k], tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
+                        tm["h2d_done"] - tm["stage_end"], tm["launch"] - max(tm["stage_end"], tm["h2d_done"]),
+                        tm["exec_begin"] - tm["launch"], tm["exec_end"] - tm["exec_begin"],
+                        tm["done"] - tm["exec_end"])
             done_max = max(done_max, tm["done"])
         s1 = srv.stats()
         runs.append({"load_fraction": frac, "offered_req_per_s": round(rate, 1), "requests": n_req,
@@ -444,7 +462,11 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
                      "p999_ms": round(float(np.percentile(lat, 99.9)) * 1e3, 3),
                      "achieved_GBps": round(payload / (done_max - start) / 1e9, 3),
                      "steps": s1["steps"] - s0["steps"], "admission_stalls": s1["stalls"] - s0["stalls"],
-                     "median_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.median(phases, 0)]})
+                     "median_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.median(phases, 0)],
+                     "p99_ms_queue_staging_device": [round(float(x) * 1e3, 3)
+                                                     for x in np.percentile(phases, 99, axis=0)],
+                     "parts_ms": {name: [round(float(np.percentile(parts[:, j], q)) * 1e3, 3) for q in (50, 99)]
+                                  for j, name in enumerate(SERVE_PARTS)}})
         print(f"bench: serving at {frac} C: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms",
               file=sys.stderr, flush=True)
     peak = srv.stats()["peak_bytes"]

@@ -251,6 +251,35 @@ int hb_server_wait(hb_server *server, uint64_t ticket, int64_t timeout_ms, int *
 int hb_server_times(hb_server *server, uint64_t ticket, double *t_submit, double *t_admit,
                     double *t_h2d_done, double *t_done);
 
+/* Per-request trace, for locating where a request's latency goes.  Fills t[0..nt) with
+ * times in seconds on the server's steady clock, in the order of the HB_TRACE_* indices
+ * (entries past HB_TRACE_COUNT are set to 0):
+ *   SUBMIT       hb_server_submit returned the ticket
+ *   ADMIT        admitted (arena range and slot reserved)
+ *   STAGE_BEGIN  a staging thread started packing it into pinned memory
+ *   STAGE_END    its last host-to-device copy was enqueued
+ *   H2D_DONE     that copy completed (device clock, mapped to the server clock)
+ *   LAUNCH       the device step holding it was enqueued
+ *   EXEC_BEGIN   that step's inputs and metadata were resident and hashing could start
+ *                (device clock)
+ *   EXEC_END     that step's digests were back in pinned host memory (device clock)
+ *   DONE         its digests were in the caller's buffer and it was marked done
+ * Times not reached yet are 0.  Returns HB_EINVAL for a null server, a negative nt, a null
+ * t with nt > 0, or an unknown ticket. */
+enum {
+    HB_TRACE_SUBMIT = 0,
+    HB_TRACE_ADMIT = 1,
+    HB_TRACE_STAGE_BEGIN = 2,
+    HB_TRACE_STAGE_END = 3,
+    HB_TRACE_H2D_DONE = 4,
+    HB_TRACE_LAUNCH = 5,
+    HB_TRACE_EXEC_BEGIN = 6,
+    HB_TRACE_EXEC_END = 7,
+    HB_TRACE_DONE = 8,
+    HB_TRACE_COUNT = 9
+};
+int hb_server_trace(hb_server *server, uint64_t ticket, double *t, int nt);
+
 /* Counters: requests completed, device steps launched, admission stalls (a queued head
  * request held back by the budget or slot limit), peak resident bytes. */
 int hb_server_stats(hb_server *server, uint64_t *completed, uint64_t *steps, uint64_t *stalls,

@@ -3,12 +3,12 @@
 // One background host thread owns the device side:
 //   admission   requests leave the FIFO in arrival order while their payload fits the
 //               device arena (the HBM budget) and a request slot is free;
-//   staging     a pool of staging threads packs each admitted request's messages into
-//               pinned double buffers and copies them into its arena range, each thread
-//               on its own copy stream (one completion event per request);
-//   steps       everything admitted and not yet launched forms the next device step,
-//               launched on the next free compute stream (each stream has its own plan),
-//               so a step can start while earlier ones are still hashing;
+//   staging     a pool of staging threads packs each admitted request's messages into a
+//               pinned ring per thread and copies them into the request's arena range, all
+//               on one copy stream (one completion event per request);
+//   steps       staged requests are batched by class (only short chains / holding a long
+//               one) into device steps on two compute streams, one per class (each with its
+//               own plan), so a step can start while another is still hashing;
 //   completion  a finished step's digests come back through pinned memory, each request
 //               is marked done, and its arena range and slot are released.
 // A request that arrives while others run is admitted as soon as memory and a slot free
@@ -44,7 +44,8 @@ constexpr double kMaxWait = 200e-6;            // ...or for its oldest request t
                                                // unless no step is running
 constexpr uint64_t kMaxStepN = 1ull << 20;     // messages per device step
 constexpr int kStagers = 4;                    // staging threads
-constexpr uint64_t kPiece = 16ull << 20;       // staging copy granularity (per buffer half)
+constexpr uint64_t kPiece = 16ull << 20;       // largest single staging copy
+constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per staging thread
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -61,7 +62,10 @@ struct Req {
     St st = St::Pending;
     int status = HB_OK;
     double t_submit = 0, t_admit = 0, t_h2d = 0, t_done = 0;
+    double t_stage_begin = 0;       // host time a staging thread took it
     double t_staged = 0;            // host time its copies were enqueued
+    double t_launch = 0;            // host time its step was launched
+    double t_exec0 = 0, t_exec1 = 0;  // its step's hashing began / digests copied (device clock)
     hipEvent_t copied = nullptr;    // last staging copy of this request
     bool stalled = false;           // was held back at the head of the queue
     int cls = 0;                    // 0: short chains only, 1: has a long chain
@@ -72,17 +76,39 @@ struct Step {
     uint64_t n = 0;
     bool mixed = false;
     int algo = 0;
+    hipEvent_t begin = nullptr;     // recorded when the step's inputs are resident
     hipEvent_t done = nullptr;
 };
 
-// A staging thread's pinned double buffer (copies go on the server's one copy stream).
-struct Stager {
-    std::thread thr;
-    uint8_t *buf = nullptr;          // 2 * kPiece pinned bytes
-    hipEvent_t half_free[2] = {nullptr, nullptr};
-    bool half_used[2] = {false, false};
+// A staging thread's pinned ring.  Each copy occupies a segment of the ring until the copy
+// completes; a new segment only waits for the oldest segments it would overwrite, so a
+// slow copy holds back the thread only once the ring is full.
+struct Segment {
+    uint64_t begin, end;
+    hipEvent_t copied;
 };
 
+struct Stager {
+    std::thread thr;
+    uint8_t *buf = nullptr;          // kRing pinned bytes
+    uint64_t head = 0;               // next free byte
+    std::deque<Segment> inflight;    // in ring order, oldest first
+    std::vector<hipEvent_t> spare;   // events of retired segments
+
+    // Reserve `want` (<= kRing) contiguous bytes; returns their offset or kRing on error.
+    uint64_t reserve(uint64_t want)
+    {
+        if (head + want > kRing) head = 0;
+        while (!inflight.empty()) {
+            const Segment &o = inflight.front();
+            if (o.end <= head || o.begin >= head + want) break;  // oldest does not overlap: none does
+            if (hipEventSynchronize(o.copied) != hipSuccess) return kRing;
+            spare.push_back(o.copied);
+            inflight.pop_front();
+        }
+        return head;
+    }
+};
 }  // namespace
 }  // namespace hb
 
@@ -150,34 +176,46 @@ double event_host_time(hb_server *s, hipEvent_t e)
 }
 
 // Pack request r's messages (back to back, index order) into its arena range through
-// stager g's pinned double buffer, copying each filled half on g's stream.  Records
-// r->copied on that stream after the last piece.
-int stage_one(hb_server *s, Stager &g, int &half, Req *r)
+// stager g's pinned ring, one copy on the copy stream per piece of at most kPiece bytes.
+// Records r->copied on that stream after the last piece.
+int stage_one(hb_server *s, Stager &g, Req *r)
 {
     uint64_t dst = r->arena_off, i = 0, within = 0;  // message index and bytes of it staged
     const uint64_t end = r->arena_off + r->payload;
     while (dst < end) {
-        const int h = half;
-        half ^= 1;
-        if (g.half_used[h]) {
-            hipError_t we = hipEventSynchronize(g.half_free[h]);
-            if (we != hipSuccess) return hip_error(we, "hb_server: staging wait");
-        }
-        uint8_t *buf = g.buf + uint64_t(h) * kPiece;
         const uint64_t want = std::min<uint64_t>(kPiece, end - dst);
+        const uint64_t at = g.reserve(want);
+        if (at == kRing) return set_error(HB_EHIP, "hb_server: staging wait");
+        uint8_t *buf = g.buf + at;
         uint64_t filled = 0;
         while (filled < want && i < r->n) {
-            const uint64_t L = r->lens[i];
-            const uint64_t take = std::min<uint64_t>(L - within, want - filled);
-            if (take) std::memcpy(buf + filled, r->msgs + r->offs[i] + within, take);
-            filled += take;
-            within += take;
-            if (within == L) { ++i; within = 0; }
+            // one copy per run of back-to-back messages (packed requests are one run)
+            const uint8_t *src = r->msgs + r->offs[i] + within;
+            uint64_t run = 0;
+            while (filled + run < want && i < r->n && r->msgs + r->offs[i] + within == src + run) {
+                const uint64_t take = std::min<uint64_t>(r->lens[i] - within, want - filled - run);
+                run += take;
+                within += take;
+                if (within == r->lens[i]) { ++i; within = 0; }
+                else break;
+            }
+            if (run) std::memcpy(buf + filled, src, run);
+            filled += run;
         }
-        hipError_t e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, s->copy_in);
-        if (e == hipSuccess) e = hipEventRecord(g.half_free[h], s->copy_in);
-        if (e != hipSuccess) return hip_error(e, "hb_server: staging copy");
-        g.half_used[h] = true;
+        hipEvent_t ev = nullptr;
+        if (!g.spare.empty()) {
+            ev = g.spare.back();
+            g.spare.pop_back();
+        }
+        hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, s->copy_in);
+        if (e == hipSuccess) e = hipEventRecord(ev, s->copy_in);
+        if (e != hipSuccess) {
+            if (ev) g.spare.push_back(ev);
+            return hip_error(e, "hb_server: staging copy");
+        }
+        g.inflight.push_back({at, at + filled, ev});
+        g.head = at + filled;
         dst += filled;
     }
     hipError_t e = hipEventCreate(&r->copied);
@@ -191,7 +229,6 @@ void stager_loop(hb_server *s, int w)
 {
     hipSetDevice(s->device);
     Stager &g = s->stager[w];
-    int half = 0;
     for (;;) {
         Req *r = nullptr;
         {
@@ -202,7 +239,8 @@ void stager_loop(hb_server *s, int w)
             s->to_stage.pop_front();
             s->staging_inflight++;
         }
-        const int rc = stage_one(s, g, half, r);
+        r->t_stage_begin = s->now();
+        const int rc = stage_one(s, g, r);
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (rc != HB_OK) r->status = rc;
@@ -250,6 +288,8 @@ int launch_step(hb_server *s, int k, int c)
         if (r->copied) hipStreamWaitEvent(s->compute[k], r->copied, 0);
         r->st = St::Launched;
     }
+    const double t_launch = s->now();
+    for (Req *r : st->reqs) r->t_launch = t_launch;
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
     uint64_t *dl = dof + kMaxStepN;
     uint8_t *di = reinterpret_cast<uint8_t *>(dl + kMaxStepN);
@@ -265,6 +305,8 @@ int launch_step(hb_server *s, int k, int c)
     if (e == hipSuccess) e = hipMemcpyAsync(dl, hl, n * 8, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess && st->mixed) e = hipMemcpyAsync(di, hi, n, hipMemcpyHostToDevice, cs);
     if (e != hipSuccess) return fail(hip_error(e, "hb_server: step metadata"));
+    st->begin = take_event(s);
+    if (!st->begin || hipEventRecord(st->begin, cs) != hipSuccess) return fail(set_error(HB_EHIP, "hb_server: step event"));
     int rc = hb_plan_run(s->plan[k], st->mixed ? di : nullptr, st->algo, s->d_arena, dof, dl, n, dd, cs);
     if (rc != HB_OK) return fail(rc);
     e = hipMemcpyAsync(hd, dd, n * stride, hipMemcpyDeviceToHost, cs);
@@ -287,8 +329,12 @@ void finish_step(hb_server *s, int k, int status)
     const uint64_t stride = st->mixed ? 32 : uint64_t(digest_size(st->algo));
     const uint8_t *hd = s->h_meta[k] + kMaxStepN * 17;
     const double t = s->now();
+    const double t_exec0 = st->begin && status == HB_OK ? event_host_time(s, st->begin) : t;
+    const double t_exec1 = st->done && status == HB_OK ? event_host_time(s, st->done) : t;
     uint64_t m = 0;
     for (Req *r : st->reqs) {
+        r->t_exec0 = t_exec0;
+        r->t_exec1 = t_exec1;
         const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
         if (r->status == HB_OK) r->status = status;
         if (r->status == HB_OK) {
@@ -304,6 +350,7 @@ void finish_step(hb_server *s, int k, int status)
         }
         if (r->payload) s->arena.release(r->arena_off, r->payload);
     }
+    if (st->begin) s->ev_pool.push_back(st->begin);
     if (st->done) s->ev_pool.push_back(st->done);
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -425,11 +472,8 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_arena), s->arena.capacity())) != hipSuccess)
         return fail(HB_ENOMEM, "hb_server_create: device arena", hipSuccess);
     for (Stager &g : s->stager) {
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&g.buf), 2 * kPiece, hipHostMallocDefault)) != hipSuccess)
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&g.buf), kRing, hipHostMallocDefault)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned staging", hipSuccess);
-        if ((e = hipEventCreateWithFlags(&g.half_free[0], hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&g.half_free[1], hipEventDisableTiming)) != hipSuccess)
-            return fail(HB_EHIP, "hb_server_create: staging stream", e);
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
@@ -547,6 +591,21 @@ int hb_server_times(hb_server *s, uint64_t ticket, double *t_submit, double *t_a
     return HB_OK;
 }
 
+int hb_server_trace(hb_server *s, uint64_t ticket, double *t, int nt)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_trace: null server");
+    if (nt < 0 || (nt > 0 && !t)) return set_error(HB_EINVAL, "hb_server_trace: null or negative-size output");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_trace: unknown ticket");
+    const Req *r = it->second.get();
+    const double v[HB_TRACE_COUNT] = {r->t_submit, r->t_admit, r->t_stage_begin, r->t_staged, r->t_h2d,
+                                      r->t_launch, r->t_exec0,  r->t_exec1,        r->t_done};
+    for (int i = 0; i < nt && i < HB_TRACE_COUNT; ++i) t[i] = v[i];
+    for (int i = HB_TRACE_COUNT; i < nt; ++i) t[i] = 0.0;
+    return HB_OK;
+}
+
 int hb_server_stats(hb_server *s, uint64_t *completed, uint64_t *nsteps, uint64_t *stalls, uint64_t *peak_bytes)
 {
     if (!s) return set_error(HB_EINVAL, "hb_server_stats: null server");
@@ -575,8 +634,11 @@ void hb_server_destroy(hb_server *s)
     s->cv_stage.notify_all();
     for (Stager &g : s->stager) {
         if (g.thr.joinable()) g.thr.join();
-        for (hipEvent_t e : g.half_free)
-            if (e) hipEventDestroy(e);
+        for (const Segment &seg : g.inflight) {
+            hipEventSynchronize(seg.copied);
+            hipEventDestroy(seg.copied);
+        }
+        for (hipEvent_t e : g.spare) hipEventDestroy(e);
         if (g.buf) hipHostFree(g.buf);
     }
     for (int k = 0; k < kStreams; ++k) {

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
             L.hb_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(_i)]
             L.hb_server_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(_i)]
             L.hb_server_times.argtypes = [_vp, _u64] + [ctypes.POINTER(ctypes.c_double)] * 4
+            L.hb_server_trace.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_double), _i]
             L.hb_server_stats.argtypes = [_vp] + [ctypes.POINTER(_u64)] * 4
             L.hb_server_now.argtypes = [_vp]
             L.hb_server_now.restype = ctypes.c_double
@@ -342,6 +343,15 @@ class Server:
         v = [ctypes.c_double() for _ in range(4)]
         check(lib().hb_server_times(self._h, ticket, *[ctypes.byref(x) for x in v]))
         return dict(zip(("submit", "admit", "h2d_done", "done"), (x.value for x in v)))
+
+    TRACE_NAMES = ("submit", "admit", "stage_begin", "stage_end", "h2d_done", "launch", "exec_begin",
+                   "exec_end", "done")
+
+    def trace(self, ticket: int) -> dict:
+        """Per-request timestamps (hb_server_trace), keyed by TRACE_NAMES."""
+        v = (ctypes.c_double * len(self.TRACE_NAMES))()
+        check(lib().hb_server_trace(self._h, ticket, v, len(self.TRACE_NAMES)))
+        return dict(zip(self.TRACE_NAMES, list(v)))
 
     def stats(self) -> dict:
         v = [_u64() for _ in range(4)]

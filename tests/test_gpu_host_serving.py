@@ -69,6 +69,13 @@ def test_serving_results_match_oracle_and_alone(hb):
     for t in tickets:
         tm = srv.times(t)
         assert tm["submit"] <= tm["admit"] <= tm["done"]
+        tr = srv.trace(t)
+        assert tr["submit"] == tm["submit"] and tr["done"] == tm["done"] and tr["h2d_done"] == tm["h2d_done"]
+        # host-clock stamps in order; device-clock stamps in order; the two clocks agree to 1 ms
+        assert tr["submit"] <= tr["admit"] <= tr["stage_begin"] <= tr["stage_end"] <= tr["launch"] <= tr["done"]
+        assert tr["exec_begin"] <= tr["exec_end"]
+        assert tr["stage_end"] - 1e-3 <= tr["h2d_done"] <= tr["exec_begin"] + 1e-3
+        assert tr["launch"] - 1e-3 <= tr["exec_begin"] and tr["exec_end"] <= tr["done"] + 1e-3
     srv.close()
 
 
