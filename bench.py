@@ -53,12 +53,16 @@ def parse():
     p.add_argument("--serve-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one plain 1 GiB device-to-device copy (reference for HBM counters)")
+    p.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="write profiles/traffic.json from the counter CSVs of two rocprofv3 runs of "
+                        "--only-headline --copy-calibration (--pmc FETCH_SIZE, then --pmc WRITE_SIZE) and exit")
     return p.parse_args()
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the plain kernels are built from (the roofline kernel)."""
     h = hashlib.sha256()
-    for f in ("hb_device.hpp", "hb_kernels.hip", "hb_plan.hip"):
+    for f in ("hb_device.hpp", "hb_kernels.hip"):
         h.update((ROOT / "paper_2407_09333_amd" / "csrc" / f).read_bytes())
     return h.hexdigest()[:16]
 
@@ -76,6 +80,41 @@ def measured_traffic(kernel: str, workload: str):
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
+
+
+def record_traffic(fetch_dir: str, write_dir: str):
+    """HBM bytes per launch of the plain fixed-length kernels from rocprofv3 counter CSVs.
+    Each counter is scaled by the factor that makes it read 1 GiB for the plain 1 GiB copy
+    kernel of the same run (the largest __amd_rocclr_copyBuffer dispatch)."""
+    import csv
+
+    def per_kernel(d):
+        f = next(Path(d).rglob("*counter_collection.csv"))
+        by = {}
+        for r in csv.DictReader(open(f)):
+            by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024)
+        return by
+
+    fetch, write = per_kernel(fetch_dir), per_kernel(write_dir)
+    copy_f = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs)
+    rf, wf = round((1 << 30) / copy_f, 3), round((1 << 30) / copy_w, 3)
+    out = {"_about": "HBM bytes per launch of the plain fixed-length kernels on 2^20 x 1,024 B, from two "
+                     "rocprofv3 runs (--pmc FETCH_SIZE, then --pmc WRITE_SIZE) of `python3 bench.py "
+                     "--only-headline --no-cpu-baseline --steps 3 --warmup 1 --copy-calibration`, written by "
+                     "`python3 bench.py --record-traffic FETCH_DIR WRITE_DIR`; each counter scaled by the factor "
+                     "that makes it read 1 GiB for the plain 1 GiB copy kernel of that run "
+                     "(__amd_rocclr_copyBuffer). source_hash = hash of hb_device.hpp and hb_kernels.hip when "
+                     "the counters were taken.",
+           "read_factor": rf, "write_factor": wf}
+    for a, name in enumerate(ALGO_NAMES):
+        k = next(k for k in fetch if f"hb::k_plain<{a}, true>" in k)
+        fb = sum(fetch[k]) / len(fetch[k]) * rf
+        wb = sum(write[k]) / len(write[k]) * wf
+        out[f"fixed:{name}"] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "source_hash": kernel_source_hash(),
+                                "bytes_per_launch": round(fb + wb), "read_over_payload": round(fb / (1 << 30), 3)}
+    TRAFFIC_FILE.write_text(json.dumps(out, indent=1) + "\n")
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline_fixed(msgs_dev, n, L, target_s):
@@ -484,6 +523,9 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: the path needs no exchange between GPUs, "
                                    "so --gpus above 1 is not run (see DESIGN.md, sharding)",
