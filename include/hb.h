@@ -203,6 +203,10 @@ void hb_plan_destroy(hb_plan *plan);
  *   algos_host      host, n x uint8 per-message ids, or NULL to use algo
  *   messages_host   host bytes; offsets_host/lengths_host host uint64 arrays
  *   digests_out_host host, n slots (stride 32 with algos_host, else digest size)
+ * A batch of at most 16 MiB of payload and at most 2^20 messages is instead hashed where
+ * it lies after packing: one plain launch reads the pinned staging buffer through its
+ * device mapping and writes the digests to pinned memory, with no copy-engine transfer
+ * (HB_HOST_ZERO_COPY_MAX, in bytes, overrides the payload limit; 0 turns this off).
  * Blocking: returns when every digest is in digests_out_host.  Allocates device and
  * pinned buffers on first use and keeps them for later calls (per thread).
  */
@@ -218,12 +222,15 @@ typedef struct hb_server hb_server;
 
 /*
  * hb_server_create -- start a serving loop on `device` with a device-memory budget of
- * hbm_budget_bytes (request payload + metadata + digests resident at once) and at most
- * max_slots requests in flight.  A background host thread admits queued requests in
- * arrival order while both limits hold, stages each admitted request's bytes into the
- * device on a copy stream, and launches hashing steps on rotating compute streams, so a
- * request arriving while others run starts as soon as memory and a slot free up and its
- * work overlaps theirs on the device.
+ * hbm_budget_bytes (request payload resident at once) and at most max_slots requests in
+ * flight.  A background host thread admits queued requests in arrival order while both
+ * limits hold; staging threads pack each admitted request's bytes into pinned memory and
+ * copy them into the device on one copy stream; staged requests are batched into hashing
+ * steps, requests holding a long chain apart from the rest, each kind on its own compute
+ * stream.  A request arriving while others run starts as soon as memory and a slot free up,
+ * and its work overlaps theirs on the device.  Returns HB_EINVAL for a null server pointer,
+ * a budget below 256 bytes or max_slots <= 0, HB_ENOMEM if the device arena or pinned
+ * buffers cannot be allocated, HB_EHIP for other runtime failures.
  */
 int hb_server_create(hb_server **server, int device, uint64_t hbm_budget_bytes, int max_slots);
 

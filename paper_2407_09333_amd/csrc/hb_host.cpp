@@ -5,10 +5,12 @@
 // buffers; the copy stream moves it to one of two device buffers; the compute stream waits
 // on the copy's event and runs the bucketed plan over the chunk; digests come back through
 // pinned memory on a third stream.  While chunk k is hashed, chunk k+1 is packed and
-// copied.
+// copied.  A small batch skips the copies: it is packed once and hashed where it lies in
+// pinned memory (zero-copy), the digests written straight to pinned memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -41,8 +43,11 @@ struct HostPipe {
     int device = -1;
     hipStream_t copy = nullptr, compute = nullptr, back = nullptr;  // H2D, hashing, D2H
     Slot slot[2];
-    hb_plan *plan = nullptr;
-    uint64_t plan_n = 0;
+    // Two plans: one without the long-chain path (no streams of its own, kept between
+    // calls) and one with it (it owns a side stream, so it is released after each call).
+    // The host sees every length, so it knows which one a batch needs.
+    hb_plan *plan = nullptr, *plan_long = nullptr;
+    uint64_t plan_n = 0, plan_long_n = 0;
 
     ~HostPipe()
     {
@@ -51,6 +56,7 @@ struct HostPipe {
         if (back) hipStreamSynchronize(back);
         for (Slot &s : slot) release(s);
         if (plan) hb_plan_destroy(plan);
+        if (plan_long) hb_plan_destroy(plan_long);
         if (copy) hipStreamDestroy(copy);
         if (compute) hipStreamDestroy(compute);
         if (back) hipStreamDestroy(back);
@@ -61,7 +67,7 @@ struct HostPipe {
         if (compute) { hipStreamSynchronize(compute); hipStreamDestroy(compute); compute = nullptr; }
         if (copy) { hipStreamSynchronize(copy); hipStreamDestroy(copy); copy = nullptr; }
         if (back) { hipStreamSynchronize(back); hipStreamDestroy(back); back = nullptr; }
-        if (plan) { hb_plan_destroy(plan); plan = nullptr; plan_n = 0; }
+        if (plan_long) { hb_plan_destroy(plan_long); plan_long = nullptr; plan_long_n = 0; }
     }
 
     static void release(Slot &s)
@@ -79,6 +85,19 @@ struct HostPipe {
 thread_local std::unique_ptr<HostPipe> t_pipe;
 
 uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Batches of at most this much payload (and at most kZeroCopyMaxN messages) are hashed
+// straight from pinned host memory: one plain launch reads the packed messages and writes
+// the digests over the host link, with no copy-engine transfer and no bucketing.
+// HB_HOST_ZERO_COPY_MAX (bytes; 0 turns the path off) overrides the payload limit.
+constexpr uint64_t kZeroCopyMax = 16ull << 20;
+constexpr uint64_t kZeroCopyMaxN = 1ull << 20;
+
+uint64_t zero_copy_max()
+{
+    if (const char *v = std::getenv("HB_HOST_ZERO_COPY_MAX")) return std::strtoull(v, nullptr, 10);
+    return kZeroCopyMax;
+}
 
 // memcpy split over up to 8 threads for large copies into pinned staging.
 void copy_parallel(uint8_t *dst, const uint8_t *src, uint64_t n)
@@ -134,6 +153,68 @@ int ensure_slot(Slot &s, uint64_t bytes, uint64_t n)
     return HB_OK;
 }
 
+// Pack messages [i0, i1) into slot s (payload back to back, rebased offsets, lengths, ids);
+// returns the payload bytes.
+uint64_t pack_chunk(Slot &s, const uint8_t *algos_host, const uint8_t *messages_host, const uint64_t *offsets_host,
+                    const uint64_t *lengths_host, uint64_t i0, uint64_t i1)
+{
+    uint64_t pos = 0;
+    // a run of back-to-back messages is copied as one range
+    bool packed = true;
+    for (uint64_t i = i0; i < i1; ++i) {
+        const uint64_t L = lengths_host[i];
+        if (i > i0 && offsets_host[i] != offsets_host[i - 1] + lengths_host[i - 1]) packed = false;
+        s.h_offs[i - i0] = pos;
+        s.h_lens[i - i0] = L;
+        if (algos_host) s.h_ids[i - i0] = algos_host[i];
+        pos += L;
+    }
+    if (packed) {
+        if (pos) copy_parallel(s.h_msgs, messages_host + offsets_host[i0], pos);
+    } else {
+        for (uint64_t i = i0; i < i1; ++i)
+            if (lengths_host[i]) std::memcpy(s.h_msgs + s.h_offs[i - i0], messages_host + offsets_host[i], lengths_host[i]);
+    }
+    return pos;
+}
+
+// Small batch: pack into pinned staging, hash it where it is (the kernels read and write
+// pinned host memory through its device mapping), copy the digests out.
+int hash_small_zero_copy(HostPipe &P, const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                         const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                         uint8_t *digests_out_host, uint64_t total_bytes)
+{
+    Slot &s = P.slot[0];
+    int rc = ensure_slot(s, total_bytes, n);
+    if (rc != HB_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (!P.compute && (e = hipStreamCreateWithFlags(&P.compute, hipStreamNonBlocking)) != hipSuccess)
+        return hip_error(e, "hash_batch_host: stream");
+    pack_chunk(s, algos_host, messages_host, offsets_host, lengths_host, 0, n);
+    void *dm = nullptr, *dd = nullptr;
+    if ((e = hipHostGetDevicePointer(&dm, s.h_msgs, 0)) != hipSuccess ||
+        (e = hipHostGetDevicePointer(&dd, s.h_dig, 0)) != hipSuccess)
+        return hip_error(e, "hash_batch_host: device mapping of pinned staging");
+    // the staging block is one allocation: payload | offsets | lengths | ids
+    uint8_t *d_msgs = static_cast<uint8_t *>(dm);
+    const uint64_t *d_offs = reinterpret_cast<const uint64_t *>(d_msgs + (reinterpret_cast<uint8_t *>(s.h_offs) - s.h_msgs));
+    const uint64_t *d_lens = reinterpret_cast<const uint64_t *>(d_msgs + (reinterpret_cast<uint8_t *>(s.h_lens) - s.h_msgs));
+    const uint8_t *d_ids = d_msgs + (s.h_ids - s.h_msgs);
+    uint8_t *d_dig = static_cast<uint8_t *>(dd);
+    const uint32_t stride = algos_host ? 32u : uint32_t(digest_size(algo));
+    if (algos_host) {
+        for (int a = 0; a < 3 && e == hipSuccess; ++a)
+            e = launch_plain(a, d_msgs, d_offs, d_lens, n, false, 0, d_dig, stride, d_ids, P.compute);
+    } else {
+        e = launch_plain(algo, d_msgs, d_offs, d_lens, n, false, 0, d_dig, stride, nullptr, P.compute);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(P.compute);
+    if (e != hipSuccess) return hip_error(e, "hash_batch_host: zero-copy hash");
+    std::memcpy(digests_out_host, s.h_dig, n * stride);
+    P.release_streams();
+    return HB_OK;
+}
+
 }  // namespace
 
 }  // namespace hb
@@ -150,10 +231,11 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         return set_error(HB_EINVAL, "hash_batch_host: null host pointer");
     if (chunk_bytes == 0) chunk_bytes = 64ull << 20;
     const uint64_t stride = algos_host ? 32 : uint64_t(digest_size(algo));
-    uint64_t any_bytes = 0;
+    uint64_t any_bytes = 0, total_bytes = 0;
     for (uint64_t i = 0; i < n; ++i) {
         if (lengths_host[i] >= (1ull << 61)) return set_error(HB_EINVAL, "hash_batch_host: length beyond 2^61");
         any_bytes |= lengths_host[i];
+        total_bytes += lengths_host[i];
     }
     if (any_bytes && !messages_host) return set_error(HB_EINVAL, "hash_batch_host: null messages");
 
@@ -164,6 +246,9 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         t_pipe.reset(new HostPipe());
         t_pipe->device = dev;
     }
+    const bool zero_copy = total_bytes <= zero_copy_max() && n <= kZeroCopyMaxN;
+    if (zero_copy) return hash_small_zero_copy(*t_pipe, algos_host, algo, messages_host, offsets_host, lengths_host, n,
+                                               digests_out_host, total_bytes);
     if (!t_pipe->copy) {
         if ((e = hipStreamCreateWithFlags(&t_pipe->copy, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipStreamCreateWithFlags(&t_pipe->compute, hipStreamNonBlocking)) != hipSuccess ||
@@ -192,12 +277,20 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
     largest_n = std::max(largest_n, n - cuts.back());
     cuts.push_back(n);
 
-    if (!P.plan || P.plan_n < largest_n) {
-        if (P.plan) hb_plan_destroy(P.plan);
-        P.plan = nullptr;
-        int rc = hb_plan_create(&P.plan, std::max<uint64_t>(largest_n, 4096), 0);
+    // the long-chain path only pays off for messages of at least HB_LONG_MIN_BLOCKS blocks
+    uint64_t long_blocks = 256;
+    if (const char *v = std::getenv("HB_LONG_MIN_BLOCKS")) long_blocks = std::strtoull(v, nullptr, 10);
+    uint64_t max_len = 0;
+    for (uint64_t i = 0; i < n; ++i) max_len = std::max(max_len, lengths_host[i]);
+    const bool want_long = (max_len + 8) / 64 + 1 >= long_blocks;
+    hb_plan *&plan = want_long ? P.plan_long : P.plan;
+    uint64_t &plan_n = want_long ? P.plan_long_n : P.plan_n;
+    if (!plan || plan_n < largest_n) {
+        if (plan) hb_plan_destroy(plan);
+        plan = nullptr;
+        int rc = hb_plan_create(&plan, std::max<uint64_t>(largest_n, 4096), want_long ? 0 : HB_PLAN_NO_LONG);
         if (rc != HB_OK) return rc;
-        P.plan_n = std::max<uint64_t>(largest_n, 4096);
+        plan_n = std::max<uint64_t>(largest_n, 4096);
     }
     for (Slot &s : P.slot) {
         int rc = ensure_slot(s, largest_chunk, largest_n);
@@ -222,23 +315,7 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         rc = drain(s);  // the slot's previous chunk must be finished before its buffers are reused
         if (rc != HB_OK) break;
         const uint64_t i0 = cuts[c], i1 = cuts[c + 1], cnt = i1 - i0;
-        uint64_t pos = 0;
-        // a run of back-to-back messages is copied as one range
-        bool packed = true;
-        for (uint64_t i = i0; i < i1; ++i) {
-            const uint64_t L = lengths_host[i];
-            if (i > i0 && offsets_host[i] != offsets_host[i - 1] + lengths_host[i - 1]) packed = false;
-            s.h_offs[i - i0] = pos;
-            s.h_lens[i - i0] = L;
-            if (algos_host) s.h_ids[i - i0] = algos_host[i];
-            pos += L;
-        }
-        if (packed) {
-            if (pos) copy_parallel(s.h_msgs, messages_host + offsets_host[i0], pos);
-        } else {
-            for (uint64_t i = i0; i < i1; ++i)
-                if (lengths_host[i]) std::memcpy(s.h_msgs + s.h_offs[i - i0], messages_host + offsets_host[i], lengths_host[i]);
-        }
+        const uint64_t pos = pack_chunk(s, algos_host, messages_host, offsets_host, lengths_host, i0, i1);
         const uint64_t bytes = pos;
         if (bytes) e = hipMemcpyAsync(s.d_msgs, s.h_msgs, bytes, hipMemcpyHostToDevice, P.copy);
         if (e == hipSuccess) e = hipMemcpyAsync(s.d_offs, s.h_offs, cnt * 8, hipMemcpyHostToDevice, P.copy);
@@ -247,7 +324,7 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         if (e == hipSuccess) e = hipEventRecord(s.copied, P.copy);
         if (e == hipSuccess) e = hipStreamWaitEvent(P.compute, s.copied, 0);
         if (e != hipSuccess) { rc = hip_error(e, "hash_batch_host: copy"); break; }
-        rc = hb_plan_run(P.plan, algos_host ? s.d_ids : nullptr, algo, s.d_msgs, s.d_offs, s.d_lens, cnt, s.d_dig,
+        rc = hb_plan_run(plan, algos_host ? s.d_ids : nullptr, algo, s.d_msgs, s.d_offs, s.d_lens, cnt, s.d_dig,
                          P.compute);
         if (rc != HB_OK) break;
         e = hipEventRecord(s.hashed, P.compute);
@@ -263,9 +340,9 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         int r2 = drain(s);
         if (rc == HB_OK) rc = r2;
     }
-    // Release the streams (and the plan's) between calls: each stream may hold one of the
-    // process's few hardware queues, and idle streams still shift which queue later streams
-    // of the caller (or of a serving loop) share.  Buffers are kept.
+    // Release the streams (and the long-chain plan's) between calls: each stream may hold
+    // one of the process's few hardware queues, and idle streams still shift which queue
+    // later streams of the caller (or of a serving loop) share.  Buffers are kept.
     P.release_streams();
     return rc;
 }

@@ -23,12 +23,38 @@ def hb():
     return _hb
 
 
+@pytest.fixture
+def zero_copy_limit():
+    """Set HB_HOST_ZERO_COPY_MAX for one test (read by the library at each call)."""
+    import os
+
+    old = os.environ.get("HB_HOST_ZERO_COPY_MAX")
+
+    def set_limit(v):
+        os.environ["HB_HOST_ZERO_COPY_MAX"] = str(v)
+
+    yield set_limit
+    if old is None:
+        os.environ.pop("HB_HOST_ZERO_COPY_MAX", None)
+    else:
+        os.environ["HB_HOST_ZERO_COPY_MAX"] = old
+
+
 @pytest.mark.parametrize("chunk", [1 << 16, 1 << 20, 64 << 20])
-def test_host_pipeline_mixed(hb, chunk):
+def test_host_pipeline_mixed(hb, zero_copy_limit, chunk):
+    zero_copy_limit(0)  # the chunked copy-engine path, whatever the batch size
     b = workloads.mixed_batch(3_000_000, seed=21, cap=1 << 17)
     print(f"case host pipeline chunk={chunk} n={b.n}", flush=True)
     got = hb.hash_batch_host(b.messages, b.offsets, b.lengths, algos=b.algos, chunk_bytes=chunk)
     assert_same(got, oracle.hash_batch(b.algos, b.messages, b.offsets, b.lengths), "host mixed")
+
+
+def test_host_default_path_mixed(hb):
+    """A 3 MB mixed batch at the default limit (hashed in place from pinned memory)."""
+    b = workloads.mixed_batch(3_000_000, seed=22, cap=1 << 17)
+    print(f"case host default path n={b.n}", flush=True)
+    got = hb.hash_batch_host(b.messages, b.offsets, b.lengths, algos=b.algos)
+    assert_same(got, oracle.hash_batch(b.algos, b.messages, b.offsets, b.lengths), "host default")
 
 
 def test_host_pipeline_single_algo_overlapping(hb):
@@ -39,6 +65,54 @@ def test_host_pipeline_single_algo_overlapping(hb):
     print("case host overlapping", flush=True)
     got = hb.hash_batch_host(data, offs, lens, algo=1, chunk_bytes=4 << 20)
     assert_same(got, oracle.hash_batch(1, data, offs, lens), "host overlapping")
+
+
+@pytest.mark.parametrize("limit", [1 << 40, 0])
+def test_host_small_batches_zero_copy_and_copy_engine(hb, zero_copy_limit, limit):
+    """Small batches hashed in place from pinned memory (limit 2^40) and through the copy
+    engine (limit 0) give the oracle's digests."""
+    zero_copy_limit(limit)
+    # 4,096 x 55 B MD5, one block each
+    data = workloads.host_random_bytes(4096 * 55, seed=1)
+    offs = np.arange(4096, dtype=np.uint64) * np.uint64(55)
+    lens = np.full(4096, 55, np.uint64)
+    print(f"case host small limit={limit} md5 4096x55", flush=True)
+    assert_same(hb.hash_batch_host(data, offs, lens, algo=0), oracle.hash_batch(0, data, offs, lens), "md5 55")
+    # every length 0..300 at odd offsets, each algorithm, then mixed with unknown ids
+    rng = np.random.default_rng(31)
+    lens = np.arange(301, dtype=np.uint64)
+    offs = (np.cumsum(lens) - lens + rng.integers(0, 7, size=lens.size).cumsum()).astype(np.uint64)
+    data = workloads.host_random_bytes(int(offs[-1] + lens[-1]) + 8, seed=32)
+    for a in range(3):
+        print(f"case host small limit={limit} algo={a} lengths 0..300", flush=True)
+        assert_same(hb.hash_batch_host(data, offs, lens, algo=a), oracle.hash_batch(a, data, offs, lens), "lengths")
+    ids = rng.integers(0, 3, size=lens.size).astype(np.uint8)
+    ids[::17] = 7
+    print(f"case host small limit={limit} mixed", flush=True)
+    valid = ids < 3
+    want = np.zeros((lens.size, 32), np.uint8)  # an unknown id gives an all-zero slot
+    want[valid] = oracle.hash_batch(ids[valid], data, offs[valid], lens[valid])
+    assert_same(hb.hash_batch_host(data, offs, lens, algos=ids), want, "mixed small")
+    # overlapping messages, and one empty batch of many empty messages
+    offs = rng.integers(0, 1000, size=500).astype(np.uint64)
+    lens = rng.integers(0, 1000, size=500).astype(np.uint64)
+    print(f"case host small limit={limit} overlapping", flush=True)
+    assert_same(hb.hash_batch_host(data, offs, lens, algo=2), oracle.hash_batch(2, data, offs, lens), "overlap")
+    z = np.zeros(3000, np.uint64)
+    assert_same(hb.hash_batch_host(data, z, z, algo=1), oracle.hash_batch(1, data, z, z), "empties")
+
+
+def test_host_zero_copy_limit_boundary(hb, zero_copy_limit):
+    """Batches just under and just over the zero-copy limit agree with each other and the
+    oracle (the two paths meet at the limit)."""
+    zero_copy_limit(64 * 1024)
+    data = workloads.host_random_bytes(64 * 1024 + 64, seed=33)
+    for n_bytes in (64 * 1024, 64 * 1024 + 64):
+        n = n_bytes // 64
+        offs = np.arange(n, dtype=np.uint64) * np.uint64(64)
+        lens = np.full(n, 64, np.uint64)
+        print(f"case host zero-copy boundary bytes={n_bytes}", flush=True)
+        assert_same(hb.hash_batch_host(data, offs, lens, algo=1), oracle.hash_batch(1, data, offs, lens), "boundary")
 
 
 def _requests(k, seed=5, rate=1e9, mixed_fraction=0.3):
