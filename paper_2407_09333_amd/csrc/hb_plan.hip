@@ -50,6 +50,7 @@ struct PlanDesc {
     int32_t sort;             // 0: one key per algorithm (index order within it)
     int32_t mpl;              // messages per lane per item
     uint32_t long_min_key;    // messages with key >= this run as long chains (0: off)
+    uint32_t bulk_margin;     // bulk sized to finish in 1/bulk_margin of the longest chain (0: no limit)
 };
 
 // Meta block (device): segment bookkeeping filled by k_scan / k_items.
@@ -64,6 +65,10 @@ struct PlanMeta {
     uint32_t long_first[4];   // first long-lane index of each algorithm (padded to 64 lanes)
     uint32_t long_blocks;     // scratch wave-blocks in use
     uint32_t max_key;         // largest key present (scans stop there)
+    uint32_t direct_n[3];     // long messages beyond the scratch, run as direct chains (they
+                              // follow the long_n scheduled ones in the segment)
+    uint32_t direct_first[4]; // first direct-lane index of each algorithm (padded to 64 lanes)
+    uint32_t bulk_waves;      // persistent-kernel waves that take items (the others exit)
 };
 
 // Device workspace (pointers fixed for the plan's life).
@@ -79,6 +84,7 @@ struct PlanWs {
     uint32_t *sched;          // scratch: kWaveBlockWords words per wave-block
     uint32_t sched_blocks;    // scratch capacity in wave-blocks
     uint32_t max_long_waves;  // capacity of wave_base (one more entry holds the end)
+    uint32_t max_direct_waves;  // direct-chain waves at most (one per SIMD)
     uint64_t max_n;
 };
 
@@ -104,6 +110,8 @@ __device__ __forceinline__ uint64_t lane_mask_lt()
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+constexpr uint64_t kMinBulkWaves = 256;  // the persistent kernel keeps at least this many
+
 // ---------------------------------------------------------------------------------------
 // Pipeline kernels
 // ---------------------------------------------------------------------------------------
@@ -117,8 +125,13 @@ __global__ __launch_bounds__(kThreads) void k_zero(PlanWs ws)
     for (uint32_t i = t; i < 3 * kBins; i += step) { ws.hist[i] = 0; ws.cursor[i] = 0; }
     if (t == 0) {
         PlanMeta *m = ws.meta;
-        for (int a = 0; a < 3; ++a) { m->count[a] = 0; m->long_n[a] = 0; m->long_first[a] = 0; }
+        for (int a = 0; a < 3; ++a) {
+            m->count[a] = 0; m->long_n[a] = 0; m->long_first[a] = 0;
+            m->direct_n[a] = 0; m->direct_first[a] = 0;
+        }
         m->long_first[3] = 0;
+        m->direct_first[3] = 0;
+        m->bulk_waves = 0xffffffffu;
         m->long_blocks = 0;
         m->max_key = 0;
         m->queue = 0;
@@ -354,12 +367,12 @@ __global__ __launch_bounds__(kThreads) void k_zero_invalid(PlanWs ws)
 // Choose the long-chain messages: within each algorithm's segment, the leading messages
 // (longest first) whose key reaches long_min_key, taken a wave (64 messages) at a time
 // while the waves' scratch regions fit; a wave's region is as many wave-blocks as its
-// first (longest) message has blocks.  One workgroup; each long-chain wave is
-// algorithm-uniform.
+// first (longest) message has blocks.  The candidates that do not fit become direct
+// chains (below).  One workgroup; each long-chain wave is algorithm-uniform.
 __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
 {
     __shared__ uint32_t part[kScanThreads];
-    __shared__ uint32_t s_run, s_wave, s_stop;
+    __shared__ uint32_t s_run, s_wave, s_stop, s_cand[3];
     const PlanDesc d = *ws.desc;
     PlanMeta *m = ws.meta;
     if (threadIdx.x == 0) { s_run = 0; s_wave = 0; }
@@ -418,6 +431,7 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
             m->long_n[a] = min(cand, taken * 64u);
             m->long_first[a] = w0 * 64u;
             s_wave = w0 + taken;
+            s_cand[a] = cand;
         }
         __syncthreads();
     }
@@ -425,6 +439,58 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
         ws.wave_base[s_wave] = s_run;  // end of the last region
         m->long_first[3] = s_wave * 64u;
         m->long_blocks = s_run;
+        // The candidates the scratch could not hold run as direct chains, each on a lane
+        // of its own at the highest priority.  At most max_direct_waves waves: if more are
+        // needed, only the messages whose chain cost (blocks x ops per block) reaches the
+        // smallest threshold that fits are taken, across the three algorithms; the rest
+        // stay with the persistent kernel.
+        uint32_t left[3];
+        for (int a = 0; a < 3; ++a) left[a] = s_cand[a] - m->long_n[a];
+        auto chosen = [&](int a, uint64_t c) -> uint32_t {  // candidates left of cost >= c
+            const uint64_t k = (c + algo_cost(a) - 1) / algo_cost(a);  // smallest key with cost >= c
+            if (k > m->max_key) return 0u;
+            const uint32_t key = uint32_t(k < 1 ? 1 : k);
+            const uint32_t ge = ws.bin_start[a * kBins + key] + ws.hist[a * kBins + key] - m->seg_pos[a];
+            return ge <= m->long_n[a] ? 0u : min(left[a], ge - m->long_n[a]);
+        };
+        auto waves = [&](uint64_t c) -> uint64_t {
+            uint64_t w = 0;
+            for (int a = 0; a < 3; ++a) w += (chosen(a, c) + 63u) / 64u;
+            return w;
+        };
+        uint64_t c = 0;
+        if (waves(0) > ws.max_direct_waves) {
+            uint64_t lo = 1, hi = uint64_t(kBins) * algo_cost(SM3) + 1;  // waves(hi) == 0
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (waves(mid) <= ws.max_direct_waves) hi = mid;
+                else lo = mid + 1;
+            }
+            c = lo;
+        }
+        uint32_t first = 0;
+        for (int o = 0; o < 3; ++o) {
+            const int a = long_order(o);
+            const uint32_t nd = c ? chosen(a, c) : left[a];
+            m->direct_n[a] = nd;
+            m->direct_first[a] = first;
+            first += (nd + 63u) & ~63u;
+        }
+        m->direct_first[3] = first;
+        // When one chain is far longer than the bulk needs, the bulk runs on fewer waves:
+        // enough that its items (total_cost, in the same op units as a chain) would finish in
+        // 1/bulk_margin of the longest chain's time at one op per wave issue slot.  Fewer
+        // bulk waves leave the long chains more issue slots and memory bandwidth.
+        uint64_t crit = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (s_cand[a] == 0) continue;
+            const uint32_t idx = ws.sorted[m->seg_pos[a]];
+            crit = max(crit, uint64_t(msg_key(d.lens[idx], d.sort)) * algo_cost(a));
+        }
+        if (crit && d.bulk_margin) {
+            const uint64_t w = (uint64_t(d.bulk_margin) * m->total_cost + crit - 1) / crit;
+            m->bulk_waves = uint32_t(min<uint64_t>(max<uint64_t>(w, kMinBulkWaves), 0xffffffffull));
+        }
     }
 }
 
@@ -486,7 +552,10 @@ __global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
 
 // Long chains, one lane per message, at the highest wave priority; each wave's lanes are
 // of one algorithm.  SCHED = 1: rounds only, from the precomputed words; SCHED = 0: the
-// ordinary compression reading the message with the next block prefetched.
+// ordinary compression reading the message with the next block prefetched.  Waves past
+// max_long_waves run the direct chains (ordinary compression) of the long messages the
+// scratch could not hold, so no long chain shares the persistent kernel's issue slots at
+// ordinary priority.
 template <int SCHED>
 __global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
 {
@@ -494,6 +563,30 @@ __global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
     const PlanMeta m = *ws.meta;
     const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t wave_first = g & ~63u;
+    if (g >= ws.max_long_waves * 64u) {
+        // direct chains: the long messages the scratch could not hold
+        const uint32_t dg = g - ws.max_long_waves * 64u;
+        if ((dg & ~63u) >= m.direct_first[3]) return;
+        int a = MD5;
+        for (int o = 0; o < 3; ++o) {
+            const int b = long_order(o);
+            const uint32_t end = o < 2 ? m.direct_first[long_order(o + 1)] : m.direct_first[3];
+            if (dg >= m.direct_first[b] && dg < end) a = b;
+        }
+        const uint32_t i = dg - m.direct_first[a];
+        if (i >= m.direct_n[a]) return;  // padding lane
+        __builtin_amdgcn_s_setprio(3);
+        const uint32_t idx = ws.sorted[m.seg_pos[a] + m.long_n[a] + i];
+        const uint8_t *msg = d.msgs + d.offs[idx];
+        const uint64_t len = d.lens[idx];
+        uint32_t st[8];
+        uint8_t *out = d.out + uint64_t(idx) * d.stride;
+        if (a == MD5) { hash_message<MD5>(msg, len, st); store_digest<MD5>(out, st, d.stride); }
+        else if (a == SHA1) { hash_message_prefetch<SHA1>(msg, len, st); store_digest<SHA1>(out, st, d.stride); }
+        else { hash_message_prefetch<SM3>(msg, len, st); store_digest<SM3>(out, st, d.stride); }
+        __builtin_amdgcn_s_setprio(0);
+        return;
+    }
     if (wave_first >= m.long_first[3]) return;
     uint32_t i = 0;
     const int a = long_algo(m, wave_first, i);
@@ -546,6 +639,7 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
     const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
     const uint64_t share = mp->total_cost / (waves ? waves : 1);
     const uint32_t lane = __lane_id();
+    if (blockIdx.x * (kThreads / 64u) + threadIdx.x / 64u >= mp->bulk_waves) return;  // surplus wave
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&ws.meta->queue, 1u);
@@ -560,7 +654,7 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
         const uint64_t cost = first == kInvalid ? 0 : uint64_t(msg_key(d.lens[first], d.sort)) * algo_cost(a) * d.mpl;
         if (cost > share) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
-        const uint32_t long_end = mp->seg_pos[a] + mp->long_n[a];  // handled by k_hash_long
+        const uint32_t long_end = mp->seg_pos[a] + mp->long_n[a] + mp->direct_n[a];  // k_hash_long's
         if (pos0 + per_item <= long_end) continue;
         for (int j = 0; j < d.mpl; ++j) {
             const uint32_t pos = pos0 + uint32_t(j) * 64u + lane;
@@ -655,6 +749,7 @@ struct hb_plan {
     bool long_on = false;           // long-chain path enabled
     bool long_sched = true;         // precomputed schedule words (else direct reads)
     uint32_t long_min_key = 0;
+    uint32_t bulk_margin = 4;     // HB_BULK_MARGIN
     hipStream_t side = nullptr;     // long-chain kernel runs here, beside the persistent kernel
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double kernel_ms_sum = 0.0;
@@ -727,7 +822,8 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         // fork: the long chains start first on the side stream and run beside the bulk
         hipEventRecord(p->ev_fork, s);
         hipStreamWaitEvent(p->side, p->ev_fork, 0);
-        const int long_blocks = int((uint64_t(ws.max_long_waves) * 64u + kThreads - 1) / kThreads);
+        const int long_blocks =
+            int((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
         if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         hipEventRecord(p->ev_join, p->side);
@@ -875,12 +971,13 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     if (const char *v = std::getenv("HB_LONG_MIN_BLOCKS")) min_blocks = std::strtoull(v, nullptr, 10);
     if (scratch_mb == 0 || min_blocks < 2 || min_blocks >= kBins) p->long_on = false;
     if (const char *v = std::getenv("HB_LONG_MODE")) p->long_sched = std::strcmp(v, "direct") != 0;
+    if (const char *v = std::getenv("HB_BULK_MARGIN")) p->bulk_margin = uint32_t(std::strtoul(v, nullptr, 10));
     uint64_t sched_blocks = 0, long_waves = 0, scratch_blocks = 0;
     if (p->long_on) {
         // wave-blocks of scratch; direct mode allocates none (the budget then only bounds
         // how many waves run as long chains)
         sched_blocks = std::min<uint64_t>(scratch_mb * (1ull << 20) / (kWaveBlockWords * 4), 0xffffffffull);
-        long_waves = sched_blocks / min_blocks + 3;
+        long_waves = std::min<uint64_t>(sched_blocks / min_blocks + 3, 1ull << 24);
         scratch_blocks = p->long_sched ? sched_blocks : 0;
         p->long_min_key = uint32_t(min_blocks);
     }
@@ -900,6 +997,7 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     p->ws.sched = reinterpret_cast<uint32_t *>(c);
     p->ws.sched_blocks = uint32_t(sched_blocks);
     p->ws.max_long_waves = uint32_t(long_waves);
+    p->ws.max_direct_waves = p->long_on ? uint32_t(p->cus) * 4u : 0u;
     p->ws.max_n = max_n;
     // Streams only where needed: each stream may take one of the process's few hardware
     // queues, and streams sharing a queue wait behind each other's kernels.
@@ -942,6 +1040,7 @@ int hb_plan_run(hb_plan *p, const uint8_t *algos, int algo, const uint8_t *messa
     d.algo = algos ? 0 : algo;
     d.sort = (p->flags & HB_PLAN_NO_SORT) ? 0 : 1;
     d.long_min_key = (p->long_on && d.sort) ? p->long_min_key : 0;
+    d.bulk_margin = p->bulk_margin;
     if ((p->flags & HB_PLAN_AUTOTUNE) && !p->tuned) {
         d.mpl = p->mpl;
         const int mask = algos ? 7 : (1 << algo);

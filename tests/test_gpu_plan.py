@@ -181,11 +181,32 @@ def _check_sampled(hb, b, idx, got, algo):
     assert_same(got[torch.from_numpy(idx).cuda()].cpu().numpy(), want, "sampled full size")
 
 
+def test_long_chain_direct_cap(hb, monkeypatch):
+    """More long candidates than direct-chain waves (one per SIMD): a cost threshold
+    across the three algorithms picks the longest chains for the long-chain kernel, the
+    rest stay in the persistent kernel.  A 1 MiB scratch holds no wave of them, so every
+    chosen one runs as a direct chain."""
+    monkeypatch.setenv("HB_LONG_SCRATCH_MB", "1")
+    monkeypatch.setenv("HB_LONG_MIN_BLOCKS", "2")
+    rng = np.random.default_rng(41)
+    n = 120_000
+    lens = rng.integers(64, 1500, size=n).astype(np.uint64)
+    lens[:300] = rng.integers(20_000, 90_000, size=300)
+    offs = workloads.packed(lens)
+    msgs = workloads.host_random_bytes(int(lens.sum()), seed=42)
+    algos = rng.integers(0, 3, size=n).astype(np.uint8)
+    print("case long path direct cap", flush=True)
+    want = oracle.hash_batch(algos, msgs, offs, lens)
+    plan = hb.Plan(n, flags=hb.PLAN_GRAPH)
+    assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "direct cap")
+    plan.close()
+
+
 @pytest.mark.parametrize("scratch_mb,min_blocks", [("1", "256"), ("512", "2"), ("1024", "16")])
 def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
     """Messages above the block threshold run as rounds-only chains from precomputed
-    schedule words; with a tiny scratch only some of them fit and the rest take the
-    ordinary path.  Every digest must match the oracle either way."""
+    schedule words; with a tiny scratch only some of them fit and the rest run as direct
+    chains.  Every digest must match the oracle either way."""
     monkeypatch.setenv("HB_LONG_SCRATCH_MB", scratch_mb)
     monkeypatch.setenv("HB_LONG_MIN_BLOCKS", min_blocks)
     rng = np.random.default_rng(int(min_blocks))
