@@ -155,8 +155,12 @@ enum {
  * first run.  Long-chain path: messages of at least HB_LONG_MIN_BLOCKS blocks (default 256,
  * i.e. about 16 KiB) have every block's schedule words computed block-parallel first, then
  * run as rounds-only chains in a high-priority kernel beside the bulk kernel (a message's
- * blocks are strictly sequential, so this shortens the critical path, not the work).
- * Returns HB_ENOMEM if the workspace cannot be allocated.
+ * blocks are strictly sequential, so this shortens the critical path, not the work);
+ * those the scratch cannot hold run there as ordinary chains, at most one wave per SIMD
+ * (the longest by blocks x ops per block), and when the longest chain dwarfs the rest the
+ * bulk kernel runs on only as many waves as finish its work in 1/HB_BULK_MARGIN (default
+ * 4; 0 = all waves) of that chain's time.  Returns HB_ENOMEM if the workspace cannot be
+ * allocated.
  */
 int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags);
 
