@@ -484,10 +484,10 @@ def bench_digits9(args):
 SERVE_PARTS = ("admit_wait", "stager_wait", "pack", "copy", "batch_wait", "exec_wait", "exec", "complete")
 
 
-def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9), cap_burst=2048):
+def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9), cap_burst=8192):
     """Open-loop Poisson arrivals; each request 1..10,000 messages (log-uniform count),
     algorithm uniform over the three, lengths log-normal (median 256 B, cap 64 KiB); device
-    budget 64 GiB.  Capacity C is measured first with a saturating burst of 2,048 requests; then requests
+    budget 64 GiB.  Capacity C is measured first with a saturating burst of 8,192 requests; then requests
     arrive at 0.5 C, 0.7 C (the headline) and 0.9 C; latency = completion time - scheduled
     arrival time (no coordinated omission)."""
     from paper_2407_09333_amd import hb, workloads

@@ -22,6 +22,10 @@ hipError_t launch_plain(int algo, const uint8_t *msgs, const uint64_t *offs, con
 
 int digest_size(int algo);
 
+// Copy `bytes` between device-accessible buffers with a kernel on `stream` (no copy
+// engine): device memory, or pinned host memory through its device mapping.
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream);
+
 // The paper's 9-digit decimal workload, generated on the device (see hash_digits9).
 hipError_t launch_digits9(int algo, uint64_t start, uint64_t n, uint8_t *out, hipStream_t stream);
 

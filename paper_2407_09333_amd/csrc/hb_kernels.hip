@@ -1,4 +1,6 @@
 // hb_kernels.hip -- plain batch-hashing kernels: one lane per message, in index order.
+#include <algorithm>
+
 #include "hb_device.hpp"
 #include "hb_internal.hpp"
 
@@ -71,6 +73,37 @@ __global__ __launch_bounds__(kPlainBlock) void k_digits9(uint64_t start, uint64_
     init_state<A>(s);
     compress<A>(s, w);
     store_digest<A>(out + i * Traits<A>::kDigest, s, Traits<A>::kDigest);
+}
+
+// Byte copy between device-accessible buffers (device memory or the device mapping of
+// pinned host memory): 16 bytes per lane per step when both ends are 16-byte aligned.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_copy(uint8_t *dst, const uint8_t *src, uint64_t n)
+{
+    const uint64_t t = uint64_t(blockIdx.x) * 256u + threadIdx.x, step = uint64_t(gridDim.x) * 256u;
+    uint64_t head = 0;
+    if constexpr (VEC) {
+        const uint64_t nv = n / 16u;
+        for (uint64_t i = t; i < nv; i += step)
+            reinterpret_cast<u32x4 *>(dst)[i] = reinterpret_cast<const u32x4 *>(src)[i];
+        head = nv * 16u;
+    }
+    for (uint64_t i = head + t; i < n; i += step) dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream)
+{
+    if (bytes == 0) return hipSuccess;
+    const bool vec = ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) == 0;
+    const uint64_t units = vec ? (bytes + 15u) / 16u : bytes;
+    const unsigned blocks = unsigned(std::min<uint64_t>((units + 255u) / 256u, 2048u));
+    if (vec)
+        hipLaunchKernelGGL(k_copy<true>, dim3(blocks), dim3(256), 0, stream, static_cast<uint8_t *>(dst),
+                           static_cast<const uint8_t *>(src), bytes);
+    else
+        hipLaunchKernelGGL(k_copy<false>, dim3(blocks), dim3(256), 0, stream, static_cast<uint8_t *>(dst),
+                           static_cast<const uint8_t *>(src), bytes);
+    return hipGetLastError();
 }
 
 hipError_t launch_digits9(int algo, uint64_t start, uint64_t n, uint8_t *out, hipStream_t stream)

@@ -639,7 +639,20 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
     const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
     const uint64_t share = mp->total_cost / (waves ? waves : 1);
     const uint32_t lane = __lane_id();
-    if (blockIdx.x * (kThreads / 64u) + threadIdx.x / 64u >= mp->bulk_waves) return;  // surplus wave
+    uint32_t bulk = mp->bulk_waves;
+    if (bulk == 0xffffffffu && d.bulk_margin && total) {
+        // no long-chain pass sized the bulk: size it from the longest item (the first in
+        // the order), by the same rule
+        const uint32_t item0 = ws.order[0];
+        int a0 = 0;
+        while (a0 < 2 && item0 >= mp->seg_item[a0 + 1]) ++a0;
+        const uint64_t crit = item0 < total ? item_cost(ws, d, *mp, a0, item0 - mp->seg_item[a0]) : 0;
+        if (crit) {
+            const uint64_t w = (uint64_t(d.bulk_margin) * mp->total_cost + crit - 1) / crit;
+            bulk = uint32_t(min<uint64_t>(max<uint64_t>(w, kMinBulkWaves), 0xffffffffull));
+        }
+    }
+    if (blockIdx.x * (kThreads / 64u) + threadIdx.x / 64u >= bulk) return;  // surplus wave
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&ws.meta->queue, 1u);

@@ -43,9 +43,11 @@ constexpr size_t kMinBatch = 8;                // a step waits for this many sta
 constexpr double kMaxWait = 200e-6;            // ...or for its oldest request to wait this long (s),
                                                // unless no step is running
 constexpr uint64_t kMaxStepN = 1ull << 20;     // messages per device step
-constexpr int kStagers = 4;                    // staging threads
+constexpr int kMaxStagers = 16;                // staging threads at most
+constexpr int kStagersDefault = 4;             // staging threads (HB_SERVER_STAGERS overrides)
 constexpr uint64_t kPiece = 16ull << 20;       // largest single staging copy
 constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per staging thread
+constexpr size_t kMaxGroup = 256;              // requests staged together at most
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -129,7 +131,8 @@ struct hb_server {
     std::deque<Req *> to_stage;     // admitted, waiting for a staging thread (under mu)
     std::vector<Req *> staged[2];   // copies enqueued, waiting for a step, by class (under mu)
     std::condition_variable cv_stage;
-    Stager stager[kStagers];
+    Stager stager[kMaxStagers];
+    int n_stagers = kStagersDefault;
     bool stop_stagers = false;
     int staging_inflight = 0;       // requests a staging thread is working on (under mu)
     // owned by the loop thread
@@ -139,7 +142,8 @@ struct hb_server {
     hipStream_t copy_in = nullptr;  // all staging copies (one hardware queue for the copies)
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams] = {};
-    uint8_t *h_meta[kStreams] = {}; // pinned: offsets | lengths | ids | digests
+    uint8_t *h_meta[kStreams] = {}; // pinned, coherent: offsets | lengths | ids | digests
+    uint8_t *m_meta[kStreams] = {}; // the same buffer through its device mapping
     uint8_t *d_meta[kStreams] = {};
     std::unique_ptr<Step> busy[kStreams];
     hipEvent_t ref = nullptr;
@@ -175,21 +179,30 @@ double event_host_time(hb_server *s, hipEvent_t e)
     return s->now();
 }
 
-// Pack request r's messages (back to back, index order) into its arena range through
-// stager g's pinned ring, one copy on the copy stream per piece of at most kPiece bytes.
-// Records r->copied on that stream after the last piece.
-int stage_one(hb_server *s, Stager &g, Req *r)
+// Pack the requests rs[0..k) (their arena ranges back to back, in that order; requests
+// without payload anywhere among them) into stager g's pinned ring and copy them into the
+// arena on the copy stream, one copy per piece of at most kPiece bytes, so a group of small
+// requests costs one transfer.  Records each request's `copied` event after the last piece.
+int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
 {
-    uint64_t dst = r->arena_off, i = 0, within = 0;  // message index and bytes of it staged
-    const uint64_t end = r->arena_off + r->payload;
-    while (dst < end) {
-        const uint64_t want = std::min<uint64_t>(kPiece, end - dst);
+    uint64_t total = 0, dst0 = 0;
+    bool have_dst = false;
+    for (int q = 0; q < k; ++q) {
+        if (rs[q]->payload && !have_dst) { dst0 = rs[q]->arena_off; have_dst = true; }
+        total += rs[q]->payload;
+    }
+    int ri = 0;
+    uint64_t i = 0, within = 0, done = 0;  // request, message in it, bytes of it staged
+    while (done < total) {
+        const uint64_t want = std::min<uint64_t>(kPiece, total - done);
         const uint64_t at = g.reserve(want);
         if (at == kRing) return set_error(HB_EHIP, "hb_server: staging wait");
         uint8_t *buf = g.buf + at;
         uint64_t filled = 0;
-        while (filled < want && i < r->n) {
-            // one copy per run of back-to-back messages (packed requests are one run)
+        while (filled < want) {
+            const Req *r = rs[ri];
+            if (i >= r->n) { ++ri; i = 0; within = 0; continue; }
+            // one memcpy per run of back-to-back messages (a packed request is one run)
             const uint8_t *src = r->msgs + r->offs[i] + within;
             uint64_t run = 0;
             while (filled + run < want && i < r->n && r->msgs + r->offs[i] + within == src + run) {
@@ -208,7 +221,7 @@ int stage_one(hb_server *s, Stager &g, Req *r)
             g.spare.pop_back();
         }
         hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMemcpyAsync(s->d_arena + dst, buf, filled, hipMemcpyHostToDevice, s->copy_in);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->d_arena + dst0 + done, buf, filled, hipMemcpyHostToDevice, s->copy_in);
         if (e == hipSuccess) e = hipEventRecord(ev, s->copy_in);
         if (e != hipSuccess) {
             if (ev) g.spare.push_back(ev);
@@ -216,37 +229,57 @@ int stage_one(hb_server *s, Stager &g, Req *r)
         }
         g.inflight.push_back({at, at + filled, ev});
         g.head = at + filled;
-        dst += filled;
+        done += filled;
     }
-    hipError_t e = hipEventCreate(&r->copied);
-    if (e == hipSuccess) e = hipEventRecord(r->copied, s->copy_in);
-    if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
+    for (int q = 0; q < k; ++q) {
+        hipError_t e = hipEventCreate(&rs[q]->copied);
+        if (e == hipSuccess) e = hipEventRecord(rs[q]->copied, s->copy_in);
+        if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
+    }
     return HB_OK;
 }
 
-// Staging thread: take admitted requests in order, stage them, hand them to the loop.
+// Staging thread: take admitted requests in order -- the head of the queue and the
+// requests after it whose arena ranges continue it, up to kPiece bytes -- stage them as
+// one group and hand them to the loop.
 void stager_loop(hb_server *s, int w)
 {
     hipSetDevice(s->device);
     Stager &g = s->stager[w];
+    std::vector<Req *> grp;
     for (;;) {
-        Req *r = nullptr;
+        grp.clear();
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_stage.wait(lk, [&] { return s->stop_stagers || !s->to_stage.empty(); });
             if (s->to_stage.empty()) return;
-            r = s->to_stage.front();
-            s->to_stage.pop_front();
-            s->staging_inflight++;
+            uint64_t bytes = 0, next = 0;
+            bool have = false;
+            while (!s->to_stage.empty() && grp.size() < kMaxGroup) {
+                Req *r = s->to_stage.front();
+                if (r->payload) {
+                    if (have && (r->arena_off != next || bytes + r->payload > kPiece)) break;
+                    next = r->arena_off + r->payload;
+                    have = true;
+                }
+                bytes += r->payload;
+                grp.push_back(r);
+                s->to_stage.pop_front();
+            }
+            s->staging_inflight += int(grp.size());
         }
-        r->t_stage_begin = s->now();
-        const int rc = stage_one(s, g, r);
+        const double t0 = s->now();
+        for (Req *r : grp) r->t_stage_begin = t0;
+        const int rc = stage_group(s, g, grp.data(), int(grp.size()));
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (rc != HB_OK) r->status = rc;
-            r->t_staged = s->now();
-            s->staged[r->cls].push_back(r);
-            s->staging_inflight--;
+            const double t1 = s->now();
+            for (Req *r : grp) {
+                if (rc != HB_OK) r->status = rc;
+                r->t_staged = t1;
+                s->staged[r->cls].push_back(r);
+            }
+            s->staging_inflight -= int(grp.size());
         }
         s->cv_work.notify_one();
     }
@@ -294,22 +327,25 @@ int launch_step(hb_server *s, int k, int c)
     uint64_t *dl = dof + kMaxStepN;
     uint8_t *di = reinterpret_cast<uint8_t *>(dl + kMaxStepN);
     uint8_t *dd = di + kMaxStepN;
-    uint8_t *hd = hi + kMaxStepN;
     hipStream_t cs = s->compute[k];
     // on failure the step is parked on stream k with no event; the loop fails its requests
     auto fail = [&](int rc) {
         s->busy[k] = std::move(st);
         return rc;
     };
-    hipError_t e = hipMemcpyAsync(dof, ho, n * 8, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess) e = hipMemcpyAsync(dl, hl, n * 8, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess && st->mixed) e = hipMemcpyAsync(di, hi, n, hipMemcpyHostToDevice, cs);
+    // Metadata in and digests out are copied by kernels on the compute stream through the
+    // pinned buffer's device mapping, not by the copy engine: a copy-engine transfer queued
+    // behind a running step would hold up the payload copies of later requests.
+    uint8_t *mm = s->m_meta[k];
+    hipError_t e = launch_copy(dof, mm, n * 8, cs);
+    if (e == hipSuccess) e = launch_copy(dl, mm + kMaxStepN * 8, n * 8, cs);
+    if (e == hipSuccess && st->mixed) e = launch_copy(di, mm + kMaxStepN * 16, n, cs);
     if (e != hipSuccess) return fail(hip_error(e, "hb_server: step metadata"));
     st->begin = take_event(s);
     if (!st->begin || hipEventRecord(st->begin, cs) != hipSuccess) return fail(set_error(HB_EHIP, "hb_server: step event"));
     int rc = hb_plan_run(s->plan[k], st->mixed ? di : nullptr, st->algo, s->d_arena, dof, dl, n, dd, cs);
     if (rc != HB_OK) return fail(rc);
-    e = hipMemcpyAsync(hd, dd, n * stride, hipMemcpyDeviceToHost, cs);
+    e = launch_copy(mm + kMaxStepN * 17, dd, n * stride, cs);
     if (e != hipSuccess) return fail(hip_error(e, "hb_server: digest copy"));
     hipEvent_t done = take_event(s);
     if (!done || hipEventRecord(done, cs) != hipSuccess) {
@@ -471,8 +507,9 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     };
     if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_arena), s->arena.capacity())) != hipSuccess)
         return fail(HB_ENOMEM, "hb_server_create: device arena", hipSuccess);
-    for (Stager &g : s->stager) {
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&g.buf), kRing, hipHostMallocDefault)) != hipSuccess)
+    if (const char *v = std::getenv("HB_SERVER_STAGERS")) s->n_stagers = std::max(1, std::min(kMaxStagers, std::atoi(v)));
+    for (int w = 0; w < s->n_stagers; ++w) {
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->stager[w].buf), kRing, hipHostMallocDefault)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned staging", hipSuccess);
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
@@ -487,9 +524,11 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
             return fail(HB_EHIP, "hb_server_create: stream", e);
         int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags);
         if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN), hipHostMallocDefault)) !=
-            hipSuccess)
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN),
+                               hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned step buffers", hipSuccess);
+        if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->m_meta[k]), s->h_meta[k], 0)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: device mapping of step buffers", e);
         if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_meta[k]), meta_bytes(kMaxStepN))) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: device step buffers", hipSuccess);
     }
@@ -498,7 +537,7 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
         return fail(HB_EHIP, "hb_server_create: reference event", e);
     s->ref_host = s->now();
     hb_server *p = s.release();
-    for (int w = 0; w < kStagers; ++w) p->stager[w].thr = std::thread(stager_loop, p, w);
+    for (int w = 0; w < p->n_stagers; ++w) p->stager[w].thr = std::thread(stager_loop, p, w);
     p->thr = std::thread(loop, p);
     *out = p;
     return HB_OK;
