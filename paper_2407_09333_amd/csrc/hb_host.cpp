@@ -3,10 +3,10 @@
 // The batch is cut into chunks of about chunk_bytes of payload.  For each chunk the host
 // packs its messages (and rebased offsets, lengths, ids) into one of two pinned staging
 // buffers; the copy stream moves it to one of two device buffers; the compute stream waits
-// on the copy's event and runs the bucketed plan over the chunk; digests come back through
-// pinned memory on a third stream.  While chunk k is hashed, chunk k+1 is packed and
-// copied.  A small batch skips the copies: it is packed once and hashed where it lies in
-// pinned memory (zero-copy), the digests written straight to pinned memory.
+// on the copy's event and runs the bucketed plan over the chunk; a kernel on the compute
+// stream writes the digests into pinned memory.  While chunk k is hashed, chunk k+1 is
+// packed and copied.  A small batch skips the copies: it is packed once and hashed where
+// it lies in pinned memory (zero-copy), the digests written straight to pinned memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,11 +29,12 @@ struct Slot {
     uint64_t *h_offs = nullptr, *h_lens = nullptr;
     uint8_t *h_ids = nullptr;
     uint8_t *h_dig = nullptr;        // pinned digests
+    uint8_t *m_dig = nullptr;        // the same, through its device mapping
     uint8_t *d_msgs = nullptr;
     uint64_t *d_offs = nullptr, *d_lens = nullptr;
     uint8_t *d_ids = nullptr, *d_dig = nullptr;
     uint64_t cap_bytes = 0, cap_n = 0;
-    hipEvent_t copied = nullptr, hashed = nullptr, drained = nullptr;
+    hipEvent_t copied = nullptr, drained = nullptr;
     // chunk bookkeeping for the drain step
     uint64_t first = 0, count = 0;
     bool busy = false;
@@ -41,7 +42,7 @@ struct Slot {
 
 struct HostPipe {
     int device = -1;
-    hipStream_t copy = nullptr, compute = nullptr, back = nullptr;  // H2D, hashing, D2H
+    hipStream_t copy = nullptr, compute = nullptr;  // H2D; hashing and the digest write-back
     Slot slot[2];
     // Two plans: one without the long-chain path (no streams of its own, kept between
     // calls) and one with it (it owns a side stream, so it is released after each call).
@@ -53,20 +54,17 @@ struct HostPipe {
     {
         if (compute) hipStreamSynchronize(compute);
         if (copy) hipStreamSynchronize(copy);
-        if (back) hipStreamSynchronize(back);
         for (Slot &s : slot) release(s);
         if (plan) hb_plan_destroy(plan);
         if (plan_long) hb_plan_destroy(plan_long);
         if (copy) hipStreamDestroy(copy);
         if (compute) hipStreamDestroy(compute);
-        if (back) hipStreamDestroy(back);
     }
 
     void release_streams()
     {
         if (compute) { hipStreamSynchronize(compute); hipStreamDestroy(compute); compute = nullptr; }
         if (copy) { hipStreamSynchronize(copy); hipStreamDestroy(copy); copy = nullptr; }
-        if (back) { hipStreamSynchronize(back); hipStreamDestroy(back); back = nullptr; }
         if (plan_long) { hb_plan_destroy(plan_long); plan_long = nullptr; plan_long_n = 0; }
     }
 
@@ -76,7 +74,6 @@ struct HostPipe {
         if (s.h_dig) hipHostFree(s.h_dig);
         if (s.d_msgs) hipFree(s.d_msgs);
         if (s.copied) hipEventDestroy(s.copied);
-        if (s.hashed) hipEventDestroy(s.hashed);
         if (s.drained) hipEventDestroy(s.drained);
         s = Slot{};
     }
@@ -131,8 +128,11 @@ int ensure_slot(Slot &s, uint64_t bytes, uint64_t n)
     hipError_t e;
     if ((e = hipHostMalloc(reinterpret_cast<void **>(&s.h_msgs), total, hipHostMallocDefault)) != hipSuccess)
         return set_error(HB_ENOMEM, "hash_batch_host: pinned staging allocation failed");
-    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s.h_dig), n * 32, hipHostMallocDefault)) != hipSuccess)
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&s.h_dig), n * 32, hipHostMallocMapped | hipHostMallocCoherent)) !=
+        hipSuccess)
         return set_error(HB_ENOMEM, "hash_batch_host: pinned digest allocation failed");
+    if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s.m_dig), s.h_dig, 0)) != hipSuccess)
+        return hip_error(e, "hash_batch_host: device mapping of pinned digests");
     void *d = nullptr;
     if ((e = hipMalloc(&d, total + n * 32)) != hipSuccess)
         return set_error(HB_ENOMEM, "hash_batch_host: device staging allocation failed");
@@ -147,7 +147,6 @@ int ensure_slot(Slot &s, uint64_t bytes, uint64_t n)
     s.cap_bytes = bytes;
     s.cap_n = n;
     if ((e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s.hashed, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&s.drained, hipEventDisableTiming)) != hipSuccess)
         return hip_error(e, "hash_batch_host: events");
     return HB_OK;
@@ -191,16 +190,15 @@ int hash_small_zero_copy(HostPipe &P, const uint8_t *algos_host, int algo, const
     if (!P.compute && (e = hipStreamCreateWithFlags(&P.compute, hipStreamNonBlocking)) != hipSuccess)
         return hip_error(e, "hash_batch_host: stream");
     pack_chunk(s, algos_host, messages_host, offsets_host, lengths_host, 0, n);
-    void *dm = nullptr, *dd = nullptr;
-    if ((e = hipHostGetDevicePointer(&dm, s.h_msgs, 0)) != hipSuccess ||
-        (e = hipHostGetDevicePointer(&dd, s.h_dig, 0)) != hipSuccess)
+    void *dm = nullptr;
+    if ((e = hipHostGetDevicePointer(&dm, s.h_msgs, 0)) != hipSuccess)
         return hip_error(e, "hash_batch_host: device mapping of pinned staging");
     // the staging block is one allocation: payload | offsets | lengths | ids
     uint8_t *d_msgs = static_cast<uint8_t *>(dm);
     const uint64_t *d_offs = reinterpret_cast<const uint64_t *>(d_msgs + (reinterpret_cast<uint8_t *>(s.h_offs) - s.h_msgs));
     const uint64_t *d_lens = reinterpret_cast<const uint64_t *>(d_msgs + (reinterpret_cast<uint8_t *>(s.h_lens) - s.h_msgs));
     const uint8_t *d_ids = d_msgs + (s.h_ids - s.h_msgs);
-    uint8_t *d_dig = static_cast<uint8_t *>(dd);
+    uint8_t *d_dig = s.m_dig;
     const uint32_t stride = algos_host ? 32u : uint32_t(digest_size(algo));
     if (algos_host) {
         for (int a = 0; a < 3 && e == hipSuccess; ++a)
@@ -251,8 +249,7 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
                                                digests_out_host, total_bytes);
     if (!t_pipe->copy) {
         if ((e = hipStreamCreateWithFlags(&t_pipe->copy, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipStreamCreateWithFlags(&t_pipe->compute, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipStreamCreateWithFlags(&t_pipe->back, hipStreamNonBlocking)) != hipSuccess) {
+            (e = hipStreamCreateWithFlags(&t_pipe->compute, hipStreamNonBlocking)) != hipSuccess) {
             t_pipe.reset();
             return hip_error(e, "hash_batch_host: streams");
         }
@@ -327,10 +324,11 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         rc = hb_plan_run(plan, algos_host ? s.d_ids : nullptr, algo, s.d_msgs, s.d_offs, s.d_lens, cnt, s.d_dig,
                          P.compute);
         if (rc != HB_OK) break;
-        e = hipEventRecord(s.hashed, P.compute);
-        if (e == hipSuccess) e = hipStreamWaitEvent(P.back, s.hashed, 0);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.h_dig, s.d_dig, cnt * stride, hipMemcpyDeviceToHost, P.back);
-        if (e == hipSuccess) e = hipEventRecord(s.drained, P.back);
+        // digests go back by a kernel through the pinned buffer's device mapping: a
+        // copy-engine transfer waiting on this chunk's hashing would hold up the next
+        // chunk's payload copy
+        e = launch_copy(s.m_dig, s.d_dig, cnt * stride, P.compute);
+        if (e == hipSuccess) e = hipEventRecord(s.drained, P.compute);
         if (e != hipSuccess) { rc = hip_error(e, "hash_batch_host: digests"); break; }
         s.first = i0;
         s.count = cnt;
