@@ -577,8 +577,9 @@ def main():
         record_traffic(*args.record_traffic)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: the path needs no exchange between GPUs, "
-                                   "so --gpus above 1 is not run (see DESIGN.md, sharding)",
+        print(json.dumps({"error": "this benchmark measures one GPU: messages are independent, so the path "
+                                   "shards across GPUs by estimated cost with no exchange while hashing, "
+                                   "and --gpus above 1 is not run",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "fixed":
