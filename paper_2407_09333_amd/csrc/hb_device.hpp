@@ -315,6 +315,32 @@ __device__ __forceinline__ void load_full_pair(const Msg &m, uint64_t blk, bool 
     }
 }
 
+// Blocks blk .. blk + 3, all wholly inside the message, from one burst of 65 dwords (two
+// whole 128-byte L2 lines per lane).
+template <bool BE>
+__device__ __forceinline__ void load_full_quad(const Msg &m, uint64_t blk, bool aligned, uint32_t w[4][16])
+{
+    const HB_GLOBAL uint32_t *q = m.p + blk * 16u;
+    uint32_t raw[65];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        u32x4 v = *reinterpret_cast<const HB_GLOBAL u32x4_a4 *>(q + 4 * k);
+        raw[4 * k + 0] = v.x; raw[4 * k + 1] = v.y; raw[4 * k + 2] = v.z; raw[4 * k + 3] = v.w;
+    }
+    if (!BE && aligned) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) w[b][i] = raw[16 * b + i];
+        return;
+    }
+    raw[64] = q[m.r ? 64 : 63];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) w[b][i] = perm(raw[16 * b + i + 1], raw[16 * b + i], m.sel);
+}
+
 // Any block of the padded message, including the tail block (message bytes, 0x80,
 // zeros), the length-only block and, when `last`, the 64-bit bit length in words 14-15
 // (low word first for MD5, high word first for SHA-1 / SM3).
@@ -362,6 +388,14 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
         // MD5 does the least work per byte, so it is the one HBM re-reads would bound:
         // whole blocks go two at a time.
         const bool aligned = __ballot(m.r != 0) == 0;
+        for (; blk + 4 <= nfast; blk += 4) {
+            uint32_t w[4][16];
+            load_full_quad<false>(m, blk, aligned, w);
+            compress<A>(s, w[0]);
+            compress<A>(s, w[1]);
+            compress<A>(s, w[2]);
+            compress<A>(s, w[3]);
+        }
         for (; blk + 2 <= nfast; blk += 2) {
             uint32_t w0[16], w1[16];
             load_full_pair<false>(m, blk, aligned, w0, w1);
