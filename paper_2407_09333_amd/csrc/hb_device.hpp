@@ -385,8 +385,8 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
     const uint64_t nb = PAD ? (m.len + 8u) / 64u + 1u : nfast;
     uint64_t blk = 0;
     if constexpr (A == MD5) {
-        // MD5 does the least work per byte, so it is the one HBM re-reads would bound:
-        // whole blocks go two at a time.
+        // MD5 does the least work per byte, so memory bounds it: whole blocks go four (then
+        // two) at a time, whole 128-byte L2 lines per lane per burst.
         const bool aligned = __ballot(m.r != 0) == 0;
         for (; blk + 4 <= nfast; blk += 4) {
             uint32_t w[4][16];
@@ -399,6 +399,15 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
         for (; blk + 2 <= nfast; blk += 2) {
             uint32_t w0[16], w1[16];
             load_full_pair<false>(m, blk, aligned, w0, w1);
+            compress<A>(s, w0);
+            compress<A>(s, w1);
+        }
+    } else {
+        // SHA-1 / SM3: two whole blocks per burst, so both halves of a 128-byte line are
+        // read before it can be evicted
+        for (; blk + 2 <= nfast; blk += 2) {
+            uint32_t w0[16], w1[16];
+            load_full_pair<true>(m, blk, false, w0, w1);
             compress<A>(s, w0);
             compress<A>(s, w1);
         }
