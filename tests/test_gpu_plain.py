@@ -54,6 +54,34 @@ def test_every_length_0_to_300_packed(hb, algo):
     assert_same(out.cpu().numpy(), oracle.hash_batch(algo, msgs, offs, lens), "packed 0..300")
 
 
+# Lengths at and around the multi-block burst boundaries (whole blocks are read four at a
+# time for MD5 and two at a time for SHA-1 / SM3, then one at a time, then the padded tail).
+BURST_EDGES = sorted({64 * k + d for k in range(1, 11) for d in (-9, -8, -1, 0, 1)} | {1023, 1024, 1025, 4095, 4096})
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_burst_boundaries_every_alignment(hb, algo):
+    """Every length around the burst boundaries, at byte offsets 0..7 (the realigning path
+    and the aligned one), packed into one batch, plus the same lengths hashed by the
+    bucketed plan."""
+    lens, offs, pos = [], [], 0
+    for r in range(8):
+        for L in BURST_EDGES:
+            pos += (r - pos) % 8  # next offset congruent to r mod 8
+            offs.append(pos)
+            lens.append(L)
+            pos += L
+    lens = np.array(lens, np.uint64)
+    offs = np.array(offs, np.uint64)
+    msgs = workloads.host_random_bytes(pos + 8, seed=47)
+    print(f"case burst boundaries algo={algo} n={lens.size}", flush=True)
+    want = oracle.hash_batch(algo, msgs, offs, lens)
+    assert_same(hb.hash_batch(algo, msgs, offs, lens).cpu().numpy(), want, "burst edges plain")
+    plan = hb.Plan(lens.size)
+    assert_same(plan.run(msgs, offs, lens, algo=algo).cpu().numpy(), want, "burst edges plan")
+    plan.close()
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 def test_uneven_uniform_0_4096(hb, algo):
     b = workloads.uniform_lengths_batch(algo, 5000, 4096, seed=3)
