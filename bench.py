@@ -404,7 +404,40 @@ def bench_ingest(args, reps=3):
             "copy_then_hash_GBps": round(payload / t_seq / 1e9, 2),
             "device_resident_GBps": round(payload / t_dev / 1e9, 1),
             "small_batches": bench_small_host_batches(),
+            "cpu_gpu_split": bench_duty_ratio(b, t_overlap),
             "note": "end-to-end rates include the host-to-device link and host copies; not the headline value"}
+
+
+def bench_duty_ratio(b, t_gpu, reps=3):
+    """The CPU + GPU split of Sec. V-D on the ingest batch (SM3, host-resident): the host
+    share's rate on its own, the fraction x* that Eq. 1-3 predict from the two rates
+    (T_cpu(x) = T_gpu(x) with T_cpu = x S / r_cpu and T_gpu = (1 - x) S / r_gpu), and a sweep
+    of x in steps of 0.02 as in Sec. V-C.  Host threads for the CPU share: half of the
+    process's cores, the other half packing the GPU share's chunks."""
+    from paper_2407_09333_amd import hb
+
+    payload = int(b.lengths.sum())
+    threads = max(1, len(os.sched_getaffinity(0)) // 2)
+    m = 1 << 16
+    hb.cpu_hash_batch(b.messages, b.offsets[:1024], b.lengths[:1024], algo=2, threads=threads)
+    t0 = time.perf_counter()
+    hb.cpu_hash_batch(b.messages, b.offsets[:m], b.lengths[:m], algo=2, threads=threads)
+    r_cpu = int(b.lengths[:m].sum()) / (time.perf_counter() - t0)
+    r_gpu = payload / t_gpu
+    x_pred = r_cpu / (r_cpu + r_gpu)
+    sweep = []
+    for k in range(11):
+        x = 0.02 * k
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            hb.hash_batch_host_split(b.messages, b.offsets, b.lengths, algo=2, cpu_fraction=x, cpu_threads=threads)
+            ts.append(time.perf_counter() - t0)
+        sweep.append({"x": round(x, 2), "ms": round(min(ts) * 1e3, 2), "GBps": round(payload / min(ts) / 1e9, 2)})
+    best = min(sweep, key=lambda r: r["ms"])
+    return {"cpu_threads": threads, "cpu_share_GBps": round(r_cpu / 1e9, 3), "gpu_path_GBps": round(r_gpu / 1e9, 2),
+            "predicted_x": round(x_pred, 4), "sweep": sweep, "best_x": best["x"], "best_GBps": best["GBps"],
+            "gain_vs_gpu_only": round(sweep[0]["ms"] / best["ms"], 3)}
 
 
 def bench_small_host_batches(reps=30):

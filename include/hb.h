@@ -218,6 +218,35 @@ int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_t *messages
                     const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
                     uint8_t *digests_out_host, uint64_t chunk_bytes);
 
+/*
+ * hash_batch_host_split -- the CPU + GPU split of Sec. V-D (Eq. 1-3): host cores hash the
+ * trailing messages that hold about cpu_fraction of the payload bytes while the GPU path
+ * of hash_batch_host hashes the others, at the same time; the call returns when both
+ * halves are in digests_out_host.  Sec. V-D picks the fraction x that balances
+ * T_cpu = N P_cpu x / N_core against T_gpu = (P_gpu / N_thread + T_alloc + T_memcpy) N (1 - x)
+ * + O_gpu; the caller passes it (hb_cpu_hash_batch measures a host rate for that).
+ *   cpu_fraction  in [0, 1]: 0 is hash_batch_host, 1 hashes everything on the host
+ *   cpu_threads   host threads for the CPU share (<= 0: all hardware threads)
+ * Other arguments and errors as hash_batch_host; HB_EINVAL for a fraction outside [0, 1].
+ * The host share is computed by host code of this library (not the GPU kernels), from the
+ * same standards, into the same digest layout.
+ */
+int hash_batch_host_split(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                          const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                          uint8_t *digests_out_host, uint64_t chunk_bytes, double cpu_fraction,
+                          int cpu_threads);
+
+/*
+ * hb_cpu_hash_batch -- the host-core hashing of hash_batch_host_split on its own: n
+ * messages in host memory on `threads` host threads (<= 0: all), digests in the layout of
+ * hash_batch_host (stride 32 with algos_host, else the digest size).  Gives the per-byte
+ * host cost P_cpu / N_core of Eq. 1.  Blocking; HB_EINVAL for an unknown algorithm or null
+ * pointers.
+ */
+int hb_cpu_hash_batch(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                      const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                      uint8_t *digests_out_host, int threads);
+
 /* ------------------------------------------------------------------------------------ */
 /* Serving: continuous batching of hash requests under an HBM budget.                    */
 /* ------------------------------------------------------------------------------------ */

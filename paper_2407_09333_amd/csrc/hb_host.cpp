@@ -344,3 +344,44 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
     P.release_streams();
     return rc;
 }
+
+extern "C" int hash_batch_host_split(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
+                                     const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,
+                                     uint8_t *digests_out_host, uint64_t chunk_bytes, double cpu_fraction,
+                                     int cpu_threads)
+{
+    if (!algos_host && digest_size(algo) == 0)
+        return set_error(HB_EINVAL, "hash_batch_host_split: unknown algorithm id");
+    if (!(cpu_fraction >= 0.0 && cpu_fraction <= 1.0))
+        return set_error(HB_EINVAL, "hash_batch_host_split: cpu_fraction must lie in [0, 1]");
+    if (n == 0) return HB_OK;
+    if (!offsets_host || !lengths_host || !digests_out_host)
+        return set_error(HB_EINVAL, "hash_batch_host_split: null host pointer");
+    uint64_t total = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (lengths_host[i] >= (1ull << 61)) return set_error(HB_EINVAL, "hash_batch_host_split: length beyond 2^61");
+        total += lengths_host[i];
+    }
+    if (total && !messages_host) return set_error(HB_EINVAL, "hash_batch_host_split: null messages");
+    // The host cores take the trailing messages holding about cpu_fraction of the payload
+    // (work grows with bytes); the GPU pipeline takes the rest, both at once.
+    uint64_t k = n;
+    if (cpu_fraction >= 1.0) k = 0;
+    else if (cpu_fraction > 0.0) {
+        const double want = cpu_fraction * double(total);
+        double tail = 0.0;
+        while (k > 0 && tail + 0.5 * double(lengths_host[k - 1]) < want) tail += double(lengths_host[--k]);
+    }
+    const uint32_t stride = algos_host ? 32u : uint32_t(digest_size(algo));
+    std::thread cpu;
+    if (k < n)
+        cpu = std::thread([=] {
+            cpu_hash_range(algos_host, algo, messages_host, offsets_host, lengths_host, k, n,
+                           digests_out_host + k * stride, stride, cpu_threads);
+        });
+    int rc = HB_OK;
+    if (k > 0) rc = hash_batch_host(algos_host, algo, messages_host, offsets_host, lengths_host, k, digests_out_host,
+                                    chunk_bytes);
+    if (cpu.joinable()) cpu.join();
+    return rc;
+}

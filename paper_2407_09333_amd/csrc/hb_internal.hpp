@@ -22,6 +22,11 @@ hipError_t launch_plain(int algo, const uint8_t *msgs, const uint64_t *offs, con
 
 int digest_size(int algo);
 
+// Hash messages [i0, i1) on host threads (the CPU share of a CPU + GPU split); message i's
+// digest goes to out + (i - i0) * stride.  threads <= 0: all hardware threads.
+void cpu_hash_range(const uint8_t *algos, int algo, const uint8_t *msgs, const uint64_t *offs, const uint64_t *lens,
+                    uint64_t i0, uint64_t i1, uint8_t *out, uint32_t stride, int threads);
+
 // Copy `bytes` between device-accessible buffers with a kernel on `stream` (no copy
 // engine): device memory, or pinned host memory through its device mapping.
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream);

@@ -68,6 +68,9 @@ def lib() -> ctypes.CDLL:
             L.hb_plan_destroy.restype = None
         if hasattr(L, "hash_batch_host"):
             L.hash_batch_host.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _u64]
+        if hasattr(L, "hash_batch_host_split"):
+            L.hash_batch_host_split.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _u64, ctypes.c_double, _i]
+            L.hb_cpu_hash_batch.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _i]
         if hasattr(L, "hb_server_create"):
             L.hb_server_create.argtypes = [ctypes.POINTER(_vp), _i, _u64, _i]
             L.hb_server_submit.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _u64, _vp,
@@ -300,6 +303,39 @@ def hash_batch_host(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarr
                                 msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
                                 lens.ctypes.data, n, out.ctypes.data, chunk_bytes))
     return out[:n]
+
+
+def _host_args(messages, offsets, lengths, algo, algos):
+    msgs = np.ascontiguousarray(messages, dtype=np.uint8).reshape(-1)
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    lens = np.ascontiguousarray(lengths, dtype=np.uint64)
+    al = np.ascontiguousarray(algos, dtype=np.uint8) if algos is not None else None
+    a = algo_id(algo) if algo is not None else 0
+    stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
+    out = np.zeros((max(offs.size, 1), stride), np.uint8)
+    return msgs, offs, lens, al, a, out
+
+
+def hash_batch_host_split(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
+                          algos: np.ndarray | None = None, cpu_fraction: float = 0.0, cpu_threads: int = 0,
+                          chunk_bytes: int = 64 << 20) -> np.ndarray:
+    """CPU + GPU split of a host-resident batch (hash_batch_host_split); numpy digests."""
+    msgs, offs, lens, al, a, out = _host_args(messages, offsets, lengths, algo, algos)
+    check(lib().hash_batch_host_split(al.ctypes.data if al is not None else None, a,
+                                      msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
+                                      lens.ctypes.data, offs.size, out.ctypes.data, chunk_bytes,
+                                      float(cpu_fraction), int(cpu_threads)))
+    return out[: offs.size]
+
+
+def cpu_hash_batch(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
+                   algos: np.ndarray | None = None, threads: int = 0) -> np.ndarray:
+    """The host-core share's hashing on its own (hb_cpu_hash_batch); numpy digests."""
+    msgs, offs, lens, al, a, out = _host_args(messages, offsets, lengths, algo, algos)
+    check(lib().hb_cpu_hash_batch(al.ctypes.data if al is not None else None, a,
+                                  msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
+                                  lens.ctypes.data, offs.size, out.ctypes.data, int(threads)))
+    return out[: offs.size]
 
 
 class Server:

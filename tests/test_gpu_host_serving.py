@@ -57,6 +57,32 @@ def test_host_default_path_mixed(hb):
     assert_same(got, oracle.hash_batch(b.algos, b.messages, b.offsets, b.lengths), "host default")
 
 
+@pytest.mark.parametrize("frac", [0.0, 0.1, 0.5, 1.0])
+def test_host_cpu_gpu_split(hb, zero_copy_limit, frac):
+    """The CPU + GPU split: host cores take the trailing messages holding about `frac` of
+    the payload, the GPU path the rest (through the copy engine here, as for a large
+    batch); the merged digests equal the oracle's."""
+    zero_copy_limit(0)
+    b = workloads.mixed_batch(4_000_000, seed=23, cap=1 << 17)
+    al = b.algos.copy()
+    al[::53] = 11
+    print(f"case host split frac={frac} n={b.n}", flush=True)
+    got = hb.hash_batch_host_split(b.messages, b.offsets, b.lengths, algos=al, cpu_fraction=frac, cpu_threads=4)
+    valid = al < 3
+    want = np.zeros((b.n, 32), np.uint8)
+    want[valid] = oracle.hash_batch(al[valid], b.messages, b.offsets[valid], b.lengths[valid])
+    assert_same(got, want, f"split {frac}")
+    single = hb.hash_batch_host_split(b.messages, b.offsets, b.lengths, algo=2, cpu_fraction=frac)
+    assert_same(single, oracle.hash_batch(2, b.messages, b.offsets, b.lengths), f"split sm3 {frac}")
+
+
+def test_host_cpu_gpu_split_rejects_bad_fraction(hb):
+    z = np.zeros(1, np.uint64)
+    with pytest.raises(hb.HBError) as e:
+        hb.hash_batch_host_split(np.zeros(1, np.uint8), z, z, algo=0, cpu_fraction=1.5)
+    assert e.value.status == hb.HB_EINVAL
+
+
 def test_host_pipeline_single_algo_overlapping(hb):
     data = workloads.host_random_bytes(200_000, seed=5)
     rng = np.random.default_rng(5)
