@@ -383,12 +383,23 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
 {
     const uint64_t nfast = m.len / 64u;
     const uint64_t nb = PAD ? (m.len + 8u) / 64u + 1u : nfast;
+    // Bursts stop at nb - 2 blocks: every lane's first nb - 2 blocks are whole (nfast is
+    // nb - 1 or nb - 2), so lanes of equal nb -- a bucketed wave -- run the burst loops the
+    // same number of times and part only for the last two blocks.  nfast and nb are
+    // per-lane values; the loops below are per-lane loops that agree when those do.
+    uint64_t nburst = PAD ? (nb >= 2u ? nb - 2u : 0u) : nfast;
+    if (PAD) {
+        // all active lanes with the same nfast (a fixed-length batch): bursts run to it
+        const int lead = __ffsll(static_cast<unsigned long long>(__ballot(1))) - 1;
+        const unsigned long long nf_lead = __shfl(static_cast<unsigned long long>(nfast), lead);
+        if (__all(nfast == nf_lead)) nburst = nfast;
+    }
     uint64_t blk = 0;
     if constexpr (A == MD5) {
         // MD5 does the least work per byte, so memory bounds it: whole blocks go four (then
         // two) at a time, whole 128-byte L2 lines per lane per burst.
         const bool aligned = __ballot(m.r != 0) == 0;
-        for (; blk + 4 <= nfast; blk += 4) {
+        for (; blk + 4 <= nburst; blk += 4) {
             uint32_t w[4][16];
             load_full_quad<false>(m, blk, aligned, w);
             compress<A>(s, w[0]);
@@ -396,7 +407,7 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
             compress<A>(s, w[2]);
             compress<A>(s, w[3]);
         }
-        for (; blk + 2 <= nfast; blk += 2) {
+        for (; blk + 2 <= nburst; blk += 2) {
             uint32_t w0[16], w1[16];
             load_full_pair<false>(m, blk, aligned, w0, w1);
             compress<A>(s, w0);
@@ -405,7 +416,7 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
     } else {
         // SHA-1 / SM3: two whole blocks per burst, so both halves of a 128-byte line are
         // read before it can be evicted
-        for (; blk + 2 <= nfast; blk += 2) {
+        for (; blk + 2 <= nburst; blk += 2) {
             uint32_t w0[16], w1[16];
             load_full_pair<true>(m, blk, false, w0, w1);
             compress<A>(s, w0);
