@@ -179,6 +179,23 @@ def test_serving_results_match_oracle_and_alone(hb):
     srv.close()
 
 
+@pytest.mark.slow
+def test_serving_benchmark_distribution_burst(hb):
+    """600 requests of the serving benchmark's own distribution (1..10,000 messages each,
+    log-normal lengths capped at 64 KiB, a third mixing algorithms per message), submitted
+    at once -- staging groups, both request classes, both compute streams and the kernel
+    copies all in play; every digest against the oracle."""
+    reqs = workloads.serving_requests(600, 1e9, seed=17, mixed_fraction=0.3)
+    print(f"case serving burst n_req={len(reqs)} msgs={sum(r.lengths.size for r in reqs)}", flush=True)
+    srv = hb.Server(hbm_budget_bytes=4 << 30, max_slots=256)
+    tickets = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in reqs]
+    outs = [srv.wait(t, timeout_ms=120_000) for t in tickets]
+    for r, o in zip(reqs, outs):
+        assert_same(o, _want(r), "serving burst")
+    assert srv.stats()["completed"] == len(reqs)
+    srv.close()
+
+
 def test_serving_budget_admission_never_overcommits(hb):
     reqs = _requests(40, seed=8, mixed_fraction=0.0)
     biggest = max(int(r.lengths.sum()) for r in reqs)
