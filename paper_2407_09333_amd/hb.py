@@ -290,19 +290,13 @@ class Plan:
 
 def hash_batch_host(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
                     algos: np.ndarray | None = None, chunk_bytes: int = 64 << 20) -> np.ndarray:
-    """Host-resident inputs: chunked H2D copies overlapped with hashing; numpy digests."""
-    msgs = np.ascontiguousarray(messages, dtype=np.uint8).reshape(-1)
-    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
-    lens = np.ascontiguousarray(lengths, dtype=np.uint64)
-    n = offs.size
-    al = np.ascontiguousarray(algos, dtype=np.uint8) if algos is not None else None
-    a = algo_id(algo) if algo is not None else 0
-    stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
-    out = np.zeros((max(n, 1), stride), np.uint8)
+    """Host-resident inputs: chunked H2D copies overlapped with hashing (zero-copy for small
+    batches); numpy digests."""
+    msgs, offs, lens, al, a, out = _host_args(messages, offsets, lengths, algo, algos)
     check(lib().hash_batch_host(al.ctypes.data if al is not None else None, a,
                                 msgs.ctypes.data if msgs.size else None, offs.ctypes.data,
-                                lens.ctypes.data, n, out.ctypes.data, chunk_bytes))
-    return out[:n]
+                                lens.ctypes.data, offs.size, out.ctypes.data, chunk_bytes))
+    return out[: offs.size]
 
 
 def _host_args(messages, offsets, lengths, algo, algos):
