@@ -443,7 +443,12 @@ __device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, 
 
 // As hash_message, with the next whole block's loads issued before the current block is
 // compressed, so a lane's memory latency is hidden behind its own compression even when
-// few waves share the SIMD.  Costs 17 VGPRs.
+// few waves share the SIMD.  Two raw buffers, loop unrolled by two: a single loop-carried
+// buffer makes the compiler land the next block in fresh registers and copy them over,
+// waiting for the loads before the compression instead of after it.  The prefetch is
+// unconditional (the last whole block is re-read at the end): loads under a branch make
+// the wait before the next block count them as possibly absent and wait for them too.
+// Costs 34 VGPRs.
 template <int A>
 __device__ __forceinline__ void hash_message_prefetch(const uint8_t *base, uint64_t len, uint32_t s[8])
 {
@@ -451,17 +456,25 @@ __device__ __forceinline__ void hash_message_prefetch(const uint8_t *base, uint6
     const uint64_t nb = (len + 8u) / 64u + 1u;
     const uint64_t nfast = len / 64u;
     init_state<A>(s);
-    uint32_t raw[17];
-    if (nfast > 0) load_raw_block(m, 0, raw);
-    for (uint64_t blk = 0; blk < nb; ++blk) {
+    uint32_t ra[17], rb[17];
+    uint64_t blk = 0;
+    if (nfast > 0) load_raw_block(m, 0, ra);
+    while (blk < nfast) {
         uint32_t w[16];
-        if (blk < nfast) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) w[i] = perm(raw[i + 1], raw[i], m.sel);
-            if (blk + 1 < nfast) load_raw_block(m, blk + 1, raw);
-        } else {
-            load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
-        }
+        for (int i = 0; i < 16; ++i) w[i] = perm(ra[i + 1], ra[i], m.sel);
+        load_raw_block(m, blk + 1 < nfast ? blk + 1 : blk, rb);
+        compress<A>(s, w);
+        if (++blk >= nfast) break;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) w[i] = perm(rb[i + 1], rb[i], m.sel);
+        load_raw_block(m, blk + 1 < nfast ? blk + 1 : blk, ra);
+        compress<A>(s, w);
+        ++blk;
+    }
+    for (; blk < nb; ++blk) {
+        uint32_t w[16];
+        load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
         compress<A>(s, w);
     }
 }

@@ -208,7 +208,8 @@ template <int A> __device__ __forceinline__ void store_sched(uint32_t *wr, uint6
 
 // The chain of a message of nb blocks whose words are in wave region wr, lane `lane`:
 // rounds only, the next block's words loaded while the current block is compressed (two
-// buffers, loop unrolled by two so no copies are needed).
+// buffers, loop unrolled by two so no copies are needed; every load unconditional so the
+// compiler's waits count them exactly).
 template <int A>
 __device__ __forceinline__ void chain_from_sched(const uint32_t *wr, uint32_t lane, uint64_t nb, uint32_t s[8])
 {
@@ -220,7 +221,9 @@ __device__ __forceinline__ void chain_from_sched(const uint32_t *wr, uint32_t la
     for (; blk + 2 <= nb; blk += 2) {
         load_sched<A>(wr, blk + 1, lane, w1);
         rounds<A>(s, w0);
-        if (blk + 2 < nb) load_sched<A>(wr, blk + 2, lane, w0);
+        // unconditional (the last block is re-read at the end): a load under a branch
+        // makes the wait before rounds(w1) count it as possibly absent and wait for it too
+        load_sched<A>(wr, blk + 2 < nb ? blk + 2 : blk + 1, lane, w0);
         rounds<A>(s, w1);
     }
     if (blk < nb) rounds<A>(s, w0);
