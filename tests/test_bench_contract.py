@@ -34,3 +34,46 @@ def test_critical_path_bound():
     # 16,385 blocks x 1,348 ops x 4 cycles at 2.1 GHz
     got = bench._critical_path_ms(lens, np.array([2, 0], np.uint8), None, clock_ghz=2.1)
     assert abs(got - 16385 * 1348 * 4 / 2.1e9 * 1e3) < 1e-9
+
+
+def test_rounds_only_critical_path():
+    import numpy as np
+
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    lens = np.array([1 << 20, 1 << 19], np.uint64)
+    got = bench._critical_path_ms(lens, np.array([2, 1], np.uint8), None, per_block=bench.ROUNDS_ONLY_OPS)
+    assert abs(got - 16385 * 921 * 4 / 2.1e9 * 1e3) < 1e-9
+
+
+def test_record_traffic_scales_by_the_copy_kernel(tmp_path, monkeypatch):
+    """Counter CSVs of two runs -> bytes per launch: each counter scaled by the factor that
+    makes the largest copy-kernel dispatch read (write) exactly 1 GiB."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    def write_csv(d, rows):
+        d.mkdir()
+        with open(d / "x_counter_collection.csv", "w") as f:
+            f.write("Kernel_Name,Counter_Value\n")
+            for name, kib in rows:
+                f.write(f'"{name}",{kib}\n')
+
+    plain = "void hb::k_plain<{}, true>(unsigned char const*, unsigned long)"
+    # the copy kernel reads 1 GiB but the counter says half of it in KiB; a small copy too
+    write_csv(tmp_path / "fetch", [("__amd_rocclr_copyBuffer", 524288), ("__amd_rocclr_copyBuffer", 10),
+                                   (plain.format(0), 512 * 1024), (plain.format(0), 512 * 1024),
+                                   (plain.format(1), 600 * 1024), (plain.format(2), 700 * 1024)])
+    write_csv(tmp_path / "write", [("__amd_rocclr_copyBuffer", 1 << 20), (plain.format(0), 16 * 1024),
+                                   (plain.format(1), 20 * 1024), (plain.format(2), 32 * 1024)])
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", out)
+    bench.record_traffic(str(tmp_path / "fetch"), str(tmp_path / "write"))
+    t = json.loads(out.read_text())
+    assert t["read_factor"] == 2.0 and t["write_factor"] == 1.0
+    assert t["fixed:md5"]["fetch_bytes"] == 1 << 30 and t["fixed:md5"]["write_bytes"] == 16 << 20
+    assert t["fixed:sm3"]["bytes_per_launch"] == 2 * 700 * (1 << 20) + (32 << 20)
+    assert t["fixed:sha1"]["source_hash"] == bench.kernel_source_hash()
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", out)
+    assert bench.measured_traffic("sm3", "fixed") == t["fixed:sm3"]["bytes_per_launch"]
