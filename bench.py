@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="fixed", choices=["fixed", "uneven", "mixed", "serve", "digits9", "ingest"])
+    p.add_argument("--workload", default="fixed",
+                   choices=["fixed", "uneven", "mixed", "serve", "digits9", "ingest", "incremental"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time in total")
     p.add_argument("--only-headline", action="store_true",
@@ -502,6 +503,44 @@ def bench_small_host_batches(reps=30):
     return res
 
 
+def bench_incremental(args, pieces=4, steps=10, warmup=2):
+    """Incremental hashing: the 2^20 x 1,024 B headline batch of each algorithm hashed in
+    `pieces` pieces per message -- init, update with whole-block pieces, final with the
+    last -- against one plain launch over whole messages; the pieces arrive in separate
+    launches with the chaining state in device memory (48 B per message)."""
+    import torch
+
+    from paper_2407_09333_amd import hb, workloads
+
+    n, L = 1 << 20, 1024
+    b = workloads.cfg_fixed_1m_x_1024(0, device="cuda", n=n)
+    stream = torch.cuda.current_stream()
+    piece = L // pieces
+    base = torch.arange(n, dtype=torch.int64, device="cuda") * L
+    lens = torch.full((n,), piece, dtype=torch.int64, device="cuda")
+    res = {"workload": f"2^20 x 1,024 B per algorithm in {pieces} pieces of {piece} B per message "
+                       f"(init + {pieces - 1} updates + final), device-resident", "pieces": pieces}
+    for a, name in enumerate(ALGO_NAMES):
+        out = torch.empty((n, hb.digest_size(a)), dtype=torch.uint8, device="cuda")
+
+        def run():
+            st = hb.hash_init(a, n, stream=stream)
+            for k in range(pieces - 1):
+                hb.hash_update(a, st, b.messages, base + k * piece, lens, stream=stream)
+            hb.hash_final(a, st, b.messages, base + (pieces - 1) * piece, lens, out=out, stream=stream)
+
+        t_inc = _time_ms(run, steps, warmup, stream)
+        got = out.clone()
+        t_one = _time_ms(lambda: hb.hash_batch_fixed(a, b.messages, n, L, out=out, stream=stream), steps, warmup,
+                         stream)
+        res[name] = {"pieces_ms": round(t_inc, 4), "one_shot_ms": round(t_one, 4),
+                     "pieces_GBps": round(n * L / t_inc / 1e6, 1), "overhead": round(t_inc / t_one, 3),
+                     "same_digests_as_one_shot": bool(torch.equal(got, out))}
+    del b
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_digits9(args):
     """The paper's workload (Sec. V-A.2): all 10^9 nine-character decimal strings, hashed
     with each algorithm; the strings are generated on the device, digests written to HBM in
@@ -650,6 +689,8 @@ def main():
             rec["ingest_host_resident"] = bench_ingest(args)
             print("bench: paper workload (10^9 nine-digit strings)", file=sys.stderr, flush=True)
             rec["paper_workload_digits9"] = bench_digits9(args)
+            print("bench: incremental hashing", file=sys.stderr, flush=True)
+            rec["incremental"] = bench_incremental(args)
             print("bench: serving", file=sys.stderr, flush=True)
             rec["serving"] = bench_serve(args, seconds=args.serve_seconds)
     elif args.workload == "uneven":
@@ -658,6 +699,8 @@ def main():
         rec = {"batched_mixed": bench_mixed(args, steps=args.steps, warmup=args.warmup)}
     elif args.workload == "ingest":
         rec = {"ingest_host_resident": bench_ingest(args)}
+    elif args.workload == "incremental":
+        rec = {"incremental": bench_incremental(args)}
     elif args.workload == "digits9":
         rec = {"paper_workload_digits9": bench_digits9(args)}
     else:
