@@ -260,7 +260,8 @@ typedef struct hb_server hb_server;
  * limits hold; staging threads pack each admitted request's bytes into pinned memory and
  * copy them into the device on one copy stream; staged requests are batched into hashing
  * steps, requests holding a long chain apart from the rest, each kind on its own compute
- * stream.  A request arriving while others run starts as soon as memory and a slot free up,
+ * stream (long-chain steps take the plan's long-chain path, see hb_plan_create; with it
+ * the server holds that path's scratch as well).  A request arriving while others run starts as soon as memory and a slot free up,
  * and its work overlaps theirs on the device.  Returns HB_EINVAL for a null server pointer,
  * a budget below 256 bytes or max_slots <= 0, HB_ENOMEM if the device arena or pinned
  * buffers cannot be allocated, HB_EHIP for other runtime failures.

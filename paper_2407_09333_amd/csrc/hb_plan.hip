@@ -976,7 +976,7 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     const uint64_t sz_desc = up(sizeof(PlanDesc)), sz_meta = up(sizeof(PlanMeta));
     const uint64_t sz_bins = up(3ull * kBins * 4);
     const uint64_t sz_sorted = up(sorted_cap * 4), sz_order = up(items_cap * 4);
-    // long-chain scratch: HB_LONG_SCRATCH_MB (default 256) of precomputed block words for
+    // long-chain scratch: HB_LONG_SCRATCH_MB (default 1024) of precomputed block words for
     // messages of at least HB_LONG_MIN_BLOCKS (default 256) blocks
     p->long_on = !(flags & HB_PLAN_NO_LONG) && !(flags & HB_PLAN_NO_SORT);
     uint64_t scratch_mb = 1024, min_blocks = 256;

@@ -514,15 +514,19 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
-    // Plans of the device steps: eager launches, no separate long-chain stream (a step's
-    // bulk is small, and every extra stream can end up sharing a hardware queue with the
-    // copy stream); HB_SERVER_PLAN_FLAGS overrides.
-    int plan_flags = HB_PLAN_NO_LONG;
-    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags = std::atoi(v);
+    // Plans of the device steps, eager launches.  Short-chain steps take no separate
+    // long-chain path (nothing in them reaches its threshold, and every extra stream can
+    // end up sharing a hardware queue with the copy stream); long-chain steps do, so their
+    // longest chains run rounds-only from precomputed schedule words beside the bulk --
+    // the chain is what such a step's latency is.  HB_SERVER_PLAN_FLAGS overrides both,
+    // HB_SERVER_LONG_PLAN_FLAGS the long-chain one.
+    int plan_flags[kStreams] = {HB_PLAN_NO_LONG, 0};
+    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags[0] = plan_flags[1] = std::atoi(v);
+    if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) plan_flags[1] = std::atoi(v);
     for (int k = 0; k < kStreams; ++k) {
         if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: stream", e);
-        int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags);
+        int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags[k]);
         if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN),
                                hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)

@@ -248,3 +248,43 @@ def test_serving_concurrent_submitters(hb):
     for i, r in enumerate(reqs):
         assert_same(results[i], _want(r), "concurrent")
     srv.close()
+
+
+def _long_chain_requests(seed=61):
+    """Requests around the long-chain thresholds: short ones, and ones holding messages of
+    255 / 256 blocks (L = 16,311 / 16,312), 64 KiB and 200,000 bytes, single-algorithm and
+    mixed."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(14):
+        cnt = int(rng.integers(1, 400))
+        lens = rng.integers(0, 3000, size=cnt).astype(np.uint64)
+        if r % 2:
+            k = min(cnt, 4)
+            lens[rng.choice(cnt, k, replace=False)] = [16_311, 16_312, 65_536, 200_000][:k]
+        offs = workloads.packed(lens)
+        msgs = workloads.host_random_bytes(int(lens.sum()), seed * 1000 + r)
+        algos = rng.integers(0, 3, size=cnt).astype(np.uint8) if r % 3 == 0 else None
+        reqs.append(workloads.Request(0.0, None if algos is not None else r % 3, algos, lens, msgs, offs))
+    return reqs
+
+
+@pytest.mark.parametrize("env", [{}, {"HB_SERVER_LONG_PLAN_FLAGS": "8"},
+                                 {"HB_LONG_MIN_BLOCKS": "2", "HB_LONG_SCRATCH_MB": "1"}],
+                         ids=["long_path", "no_long_path", "direct_chains"])
+def test_serving_long_chain_steps(hb, monkeypatch, env):
+    """Requests holding long chains go to long-chain steps, whose plan runs the longest
+    chains rounds-only from precomputed schedule words (or, with a scratch too small for
+    them, as direct chains) beside the bulk; with the path switched off they stay in the
+    persistent kernel.  Every digest against the oracle either way."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    reqs = _long_chain_requests()
+    print(f"case serving long chains env={env}", flush=True)
+    srv = hb.Server(hbm_budget_bytes=1 << 30, max_slots=64)
+    tickets = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in reqs]
+    outs = [srv.wait(t, timeout_ms=60_000) for t in tickets]
+    for r, o in zip(reqs, outs):
+        assert_same(o, _want(r), "serving long chains")
+    assert srv.stats()["completed"] == len(reqs)
+    srv.close()
