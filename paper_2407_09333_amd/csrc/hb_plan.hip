@@ -831,7 +831,14 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         if (p->long_sched) hipLaunchKernelGGL(k_sched, dim3(g), dim3(kThreads), 0, s, ws);
     }
     if (ev.first) hipEventRecord(ev.first, s);
-    if (p->long_on) {
+    const bool inline_long = p->long_on && !p->side;
+    if (inline_long) {
+        // no side stream: the long chains run first, then the bulk with all its waves
+        const int long_blocks =
+            int((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
+        if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, s, ws);
+        else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, s, ws);
+    } else if (p->long_on) {
         // fork: the long chains start first on the side stream and run beside the bulk
         hipEventRecord(p->ev_fork, s);
         hipStreamWaitEvent(p->side, p->ev_fork, 0);
@@ -845,7 +852,7 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
     else
         hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
-    if (p->long_on) hipStreamWaitEvent(s, p->ev_join, 0);  // join
+    if (p->long_on && !inline_long) hipStreamWaitEvent(s, p->ev_join, 0);  // join
     if (ev.first) {
         hipEventRecord(ev.second, s);
         p->ev_pending.push_back(ev);
@@ -1016,7 +1023,7 @@ int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags)
     // queues, and streams sharing a queue wait behind each other's kernels.
     e = hipSuccess;
     if (flags & HB_PLAN_GRAPH) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-    if (e == hipSuccess && p->long_on) {
+    if (e == hipSuccess && p->long_on && !(flags & HB_PLAN_LONG_INLINE)) {
         if ((e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking)) == hipSuccess &&
             (e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming)) == hipSuccess)
             e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
@@ -1053,7 +1060,8 @@ int hb_plan_run(hb_plan *p, const uint8_t *algos, int algo, const uint8_t *messa
     d.algo = algos ? 0 : algo;
     d.sort = (p->flags & HB_PLAN_NO_SORT) ? 0 : 1;
     d.long_min_key = (p->long_on && d.sort) ? p->long_min_key : 0;
-    d.bulk_margin = p->bulk_margin;
+    // no bulk sizing when the long chains run before the bulk instead of beside it
+    d.bulk_margin = (p->long_on && !p->side) ? 0 : p->bulk_margin;
     if ((p->flags & HB_PLAN_AUTOTUNE) && !p->tuned) {
         d.mpl = p->mpl;
         const int mask = algos ? 7 : (1 << algo);

@@ -3,11 +3,12 @@
 // One background host thread owns the device side:
 //   admission   requests leave the FIFO in arrival order while their payload fits the
 //               device arena (the HBM budget) and a request slot is free;
-//   staging     a pool of staging threads packs each admitted request's messages into a
-//               pinned ring per thread and copies them into the request's arena range, all
-//               on one copy stream (one completion event per request);
+//   staging     a pool of staging threads packs admitted requests -- a run of them whose
+//               arena ranges follow each other at a time -- into a pinned ring per thread
+//               and copies each run into the arena with one transfer, all on one copy
+//               stream (one completion mark per run);
 //   steps       staged requests are batched by class (only short chains / holding a long
-//               one) into device steps on two compute streams, one per class (each with its
+//               one) into device steps on compute streams of their class (each with its
 //               own plan), so a step can start while another is still hashing;
 //   completion  a finished step's digests come back through pinned memory, each request
 //               is marked done, and its arena range and slot are released.
@@ -32,11 +33,15 @@
 #include "../../include/hb.h"
 #include "hb_arena.hpp"
 #include "hb_internal.hpp"
+#include "hb_stage.hpp"
 
 namespace hb {
 namespace {
 
-constexpr int kStreams = 2;                    // compute streams: 0 short requests, 1 long
+constexpr int kStreams = 8;                    // compute streams at most: 0 short requests,
+                                               // the others long ones
+constexpr int kLongStreamsDefault = 1;
+inline int stream_class(int k) { return k == 0 ? 0 : 1; }
 constexpr uint64_t kLongChain = 128 * 1350;    // a request is "long" if its longest message's
                                                // chain exceeds this many ops (128 SM3 blocks)
 constexpr size_t kMinBatch = 8;                // a step waits for this many staged requests...
@@ -50,6 +55,21 @@ constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per stagin
 constexpr size_t kMaxGroup = 256;              // requests staged together at most
 
 enum class St { Pending, Admitted, Launched, Done };
+
+// Completion mark of one staged group's copies: an event recorded on the copy stream after
+// the group's last piece, shared by the group's requests.
+struct CopyMark {
+    hipEvent_t ev = nullptr;
+    uint64_t seq = 0;   // position among the marks on the copy stream
+    double t = -1;      // host time of ev, once read
+    CopyMark() = default;
+    CopyMark(const CopyMark &) = delete;
+    CopyMark &operator=(const CopyMark &) = delete;
+    ~CopyMark()
+    {
+        if (ev) hipEventDestroy(ev);
+    }
+};
 
 struct Req {
     uint64_t ticket = 0;
@@ -68,7 +88,7 @@ struct Req {
     double t_staged = 0;            // host time its copies were enqueued
     double t_launch = 0;            // host time its step was launched
     double t_exec0 = 0, t_exec1 = 0;  // its step's hashing began / digests copied (device clock)
-    hipEvent_t copied = nullptr;    // last staging copy of this request
+    std::shared_ptr<CopyMark> copied;  // its staging group's copies
     bool stalled = false;           // was held back at the head of the queue
     int cls = 0;                    // 0: short chains only, 1: has a long chain
 };
@@ -93,6 +113,7 @@ struct Segment {
 struct Stager {
     std::thread thr;
     uint8_t *buf = nullptr;          // kRing pinned bytes
+    uint8_t *dbuf = nullptr;         // their device mapping (kernel copies)
     uint64_t head = 0;               // next free byte
     std::deque<Segment> inflight;    // in ring order, oldest first
     std::vector<hipEvent_t> spare;   // events of retired segments
@@ -100,6 +121,7 @@ struct Stager {
     // Reserve `want` (<= kRing) contiguous bytes; returns their offset or kRing on error.
     uint64_t reserve(uint64_t want)
     {
+        head = (head + 255) & ~uint64_t(255);  // copies start 256-byte aligned
         if (head + want > kRing) head = 0;
         while (!inflight.empty()) {
             const Segment &o = inflight.front();
@@ -140,12 +162,16 @@ struct hb_server {
     uint8_t *d_arena = nullptr;
     std::vector<hipEvent_t> ev_pool;
     hipStream_t copy_in = nullptr;  // all staging copies (one hardware queue for the copies)
+    bool copy_kernel = false;       // payload copies by kernel from the rings' device mapping
+    std::mutex copy_mu;             // orders the copy marks' records on copy_in
+    uint64_t copy_seq = 0;          // (under copy_mu)
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams] = {};
     uint8_t *h_meta[kStreams] = {}; // pinned, coherent: offsets | lengths | ids | digests
     uint8_t *m_meta[kStreams] = {}; // the same buffer through its device mapping
     uint8_t *d_meta[kStreams] = {};
     std::unique_ptr<Step> busy[kStreams];
+    int n_streams = kStreams;       // compute streams in use
     hipEvent_t ref = nullptr;
     double ref_host = 0;
     std::chrono::steady_clock::time_point t0;
@@ -179,49 +205,29 @@ double event_host_time(hb_server *s, hipEvent_t e)
     return s->now();
 }
 
-// Pack the requests rs[0..k) (their arena ranges back to back, in that order; requests
-// without payload anywhere among them) into stager g's pinned ring and copy them into the
-// arena on the copy stream, one copy per piece of at most kPiece bytes, so a group of small
-// requests costs one transfer.  Records each request's `copied` event after the last piece.
+// Pack the group rs[0..k) (arena ranges following each other, see GroupPacker) into
+// stager g's pinned ring and copy it into the arena on the copy stream, one copy per piece
+// of at most kPiece bytes, so a group of small requests costs one transfer.  One mark
+// recorded after the last piece is shared by the group's requests.
 int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
 {
-    uint64_t total = 0, dst0 = 0;
-    bool have_dst = false;
-    for (int q = 0; q < k; ++q) {
-        if (rs[q]->payload && !have_dst) { dst0 = rs[q]->arena_off; have_dst = true; }
-        total += rs[q]->payload;
-    }
-    int ri = 0;
-    uint64_t i = 0, within = 0, done = 0;  // request, message in it, bytes of it staged
-    while (done < total) {
-        const uint64_t want = std::min<uint64_t>(kPiece, total - done);
+    GroupPacker<Req> pk(rs, k);
+    while (pk.done() < pk.total()) {
+        const uint64_t want = std::min<uint64_t>(kPiece, pk.total() - pk.done());
         const uint64_t at = g.reserve(want);
         if (at == kRing) return set_error(HB_EHIP, "hb_server: staging wait");
-        uint8_t *buf = g.buf + at;
-        uint64_t filled = 0;
-        while (filled < want) {
-            const Req *r = rs[ri];
-            if (i >= r->n) { ++ri; i = 0; within = 0; continue; }
-            // one memcpy per run of back-to-back messages (a packed request is one run)
-            const uint8_t *src = r->msgs + r->offs[i] + within;
-            uint64_t run = 0;
-            while (filled + run < want && i < r->n && r->msgs + r->offs[i] + within == src + run) {
-                const uint64_t take = std::min<uint64_t>(r->lens[i] - within, want - filled - run);
-                run += take;
-                within += take;
-                if (within == r->lens[i]) { ++i; within = 0; }
-                else break;
-            }
-            if (run) std::memcpy(buf + filled, src, run);
-            filled += run;
-        }
+        const uint64_t dst = pk.dst0() + pk.done();
+        const uint64_t filled = pk.next(g.buf + at, want);
+        if (filled != want) return set_error(HB_EINVAL, "hb_server: request shorter than its lengths");
         hipEvent_t ev = nullptr;
         if (!g.spare.empty()) {
             ev = g.spare.back();
             g.spare.pop_back();
         }
         hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMemcpyAsync(s->d_arena + dst0 + done, buf, filled, hipMemcpyHostToDevice, s->copy_in);
+        if (e == hipSuccess)
+            e = s->copy_kernel ? launch_copy(s->d_arena + dst, g.dbuf + at, filled, s->copy_in)
+                               : hipMemcpyAsync(s->d_arena + dst, g.buf + at, filled, hipMemcpyHostToDevice, s->copy_in);
         if (e == hipSuccess) e = hipEventRecord(ev, s->copy_in);
         if (e != hipSuccess) {
             if (ev) g.spare.push_back(ev);
@@ -229,19 +235,22 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
         }
         g.inflight.push_back({at, at + filled, ev});
         g.head = at + filled;
-        done += filled;
     }
-    for (int q = 0; q < k; ++q) {
-        hipError_t e = hipEventCreate(&rs[q]->copied);
-        if (e == hipSuccess) e = hipEventRecord(rs[q]->copied, s->copy_in);
-        if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
+    auto mark = std::make_shared<CopyMark>();
+    hipError_t e = hipEventCreate(&mark->ev);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->copy_mu);
+        e = hipEventRecord(mark->ev, s->copy_in);
+        mark->seq = ++s->copy_seq;
     }
+    if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
+    for (int q = 0; q < k; ++q) rs[q]->copied = mark;
     return HB_OK;
 }
 
 // Staging thread: take admitted requests in order -- the head of the queue and the
-// requests after it whose arena ranges continue it, up to kPiece bytes -- stage them as
-// one group and hand them to the loop.
+// requests after it whose arena ranges continue it (up to the allocator's alignment), up
+// to kPiece bytes -- stage them as one group and hand them to the loop.
 void stager_loop(hb_server *s, int w)
 {
     hipSetDevice(s->device);
@@ -259,10 +268,10 @@ void stager_loop(hb_server *s, int w)
                 Req *r = s->to_stage.front();
                 if (r->payload) {
                     if (have && (r->arena_off != next || bytes + r->payload > kPiece)) break;
-                    next = r->arena_off + r->payload;
+                    next = r->arena_off + Arena::round_up(r->payload);  // where the next range starts
                     have = true;
+                    bytes += Arena::round_up(r->payload);
                 }
-                bytes += r->payload;
                 grp.push_back(r);
                 s->to_stage.pop_front();
             }
@@ -310,6 +319,7 @@ int launch_step(hb_server *s, int k, int c)
     uint64_t *hl = ho + kMaxStepN;
     uint8_t *hi = reinterpret_cast<uint8_t *>(hl + kMaxStepN);
     uint64_t m = 0;
+    const CopyMark *last = nullptr;
     for (Req *r : st->reqs) {
         uint64_t pos = r->arena_off;
         for (uint64_t i = 0; i < r->n; ++i, ++m) {
@@ -318,9 +328,12 @@ int launch_step(hb_server *s, int k, int c)
             hi[m] = uint8_t(r->algo < 0 ? r->algos[i] : r->algo);
             pos += r->lens[i];
         }
-        if (r->copied) hipStreamWaitEvent(s->compute[k], r->copied, 0);
+        if (r->copied && (!last || r->copied->seq > last->seq)) last = r->copied.get();
         r->st = St::Launched;
     }
+    // the copy stream is in order: once the step's latest mark is reached, every copy the
+    // step reads has landed
+    if (last) hipStreamWaitEvent(s->compute[k], last->ev, 0);
     const double t_launch = s->now();
     for (Req *r : st->reqs) r->t_launch = t_launch;
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
@@ -380,9 +393,10 @@ void finish_step(hb_server *s, int k, int status)
         }
         m += r->n;
         if (r->copied) {
-            r->t_h2d = r->status == HB_OK ? event_host_time(s, r->copied) : t;
-            hipEventDestroy(r->copied);
-            r->copied = nullptr;
+            CopyMark &c = *r->copied;
+            if (r->status == HB_OK && c.t < 0) c.t = event_host_time(s, c.ev);
+            r->t_h2d = r->status == HB_OK ? c.t : t;
+            r->copied.reset();
         }
         if (r->payload) s->arena.release(r->arena_off, r->payload);
     }
@@ -407,7 +421,8 @@ void loop(hb_server *s)
     for (;;) {
         // 1. admission, in arrival order; admitted requests go to the staging threads
         size_t admitted = 0;
-        int launch_cls[kStreams] = {-1, -1};  // class to launch on each idle stream
+        int launch_cls[kStreams];  // class to launch on each idle stream
+        std::fill(launch_cls, launch_cls + kStreams, -1);
         {
             std::unique_lock<std::mutex> g(s->mu);
             bool any_busy = false;
@@ -438,25 +453,37 @@ void loop(hb_server *s)
                 s->stalls++;
             }
             if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
-            // continuous batching: stream k serves class k; a step is launched when its
-            // stream is idle and either no step is running, enough requests are staged, or
-            // the oldest has waited long enough.  An idle stream whose class has nothing
-            // staged takes the other class's requests while that class's stream is busy.
+            // continuous batching: stream 0 serves short requests, the others long ones; a
+            // step is launched when one of its class's streams is idle and either no step is
+            // running, enough requests are staged, or the oldest has waited long enough (one
+            // step per class at a time).  An idle stream whose class has nothing staged takes
+            // the other class's requests while all of that class's streams are busy.
             const double now = s->now();
             auto ready = [&](int c) {
                 const std::vector<Req *> &q = s->staged[c];
                 return !q.empty() && (!any_busy || q.size() >= kMinBatch || now - q.front()->t_staged >= kMaxWait);
             };
-            for (int k = 0; k < kStreams; ++k) {
+            auto all_busy = [&](int c) {
+                for (int k = 0; k < s->n_streams; ++k)
+                    if (stream_class(k) == c && !s->busy[k]) return false;
+                return true;
+            };
+            bool launched[2] = {false, false};
+            for (int k = 0; k < s->n_streams; ++k) {
                 if (s->busy[k]) continue;
-                if (ready(k)) launch_cls[k] = k;
-                else if (s->staged[k].empty() && s->busy[1 - k] && ready(1 - k)) launch_cls[k] = 1 - k;
+                const int c = stream_class(k), o = 1 - c;
+                if (!launched[c] && ready(c)) {
+                    launch_cls[k] = c;
+                    launched[c] = true;
+                } else if (s->staged[c].empty() && !launched[o] && all_busy(o) && ready(o)) {
+                    launch_cls[k] = o;
+                    launched[o] = true;
+                }
             }
-            if (launch_cls[0] >= 0 && launch_cls[0] == launch_cls[1]) launch_cls[1] = -1;
         }
         if (admitted) s->cv_stage.notify_all();
         // 2. launch steps on idle compute streams
-        for (int k = 0; k < kStreams; ++k) {
+        for (int k = 0; k < s->n_streams; ++k) {
             if (launch_cls[k] < 0) continue;
             int rc = launch_step(s, k, launch_cls[k]);
             if (rc != HB_OK) {
@@ -469,7 +496,7 @@ void loop(hb_server *s)
         }
         // 3. completions
         bool progressed = false;
-        for (int k = 0; k < kStreams; ++k) {
+        for (int k = 0; k < s->n_streams; ++k) {
             if (!s->busy[k]) continue;
             hipError_t q = hipEventQuery(s->busy[k]->done);
             if (q == hipSuccess) { finish_step(s, k, HB_OK); progressed = true; }
@@ -508,22 +535,36 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_arena), s->arena.capacity())) != hipSuccess)
         return fail(HB_ENOMEM, "hb_server_create: device arena", hipSuccess);
     if (const char *v = std::getenv("HB_SERVER_STAGERS")) s->n_stagers = std::max(1, std::min(kMaxStagers, std::atoi(v)));
+    if (const char *v = std::getenv("HB_SERVER_COPY")) s->copy_kernel = std::strcmp(v, "kernel") == 0;
     for (int w = 0; w < s->n_stagers; ++w) {
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->stager[w].buf), kRing, hipHostMallocDefault)) != hipSuccess)
+        const unsigned fl = s->copy_kernel ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->stager[w].buf), kRing, fl)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned staging", hipSuccess);
+        if (s->copy_kernel &&
+            (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->stager[w].dbuf), s->stager[w].buf, 0)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: device mapping of staging", e);
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
-    // Plans of the device steps, eager launches.  Short-chain steps take no separate
-    // long-chain path (nothing in them reaches its threshold, and every extra stream can
-    // end up sharing a hardware queue with the copy stream); long-chain steps do, so their
-    // longest chains run rounds-only from precomputed schedule words beside the bulk --
-    // the chain is what such a step's latency is.  HB_SERVER_PLAN_FLAGS overrides both,
-    // HB_SERVER_LONG_PLAN_FLAGS the long-chain one.
-    int plan_flags[kStreams] = {HB_PLAN_NO_LONG, 0};
-    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags[0] = plan_flags[1] = std::atoi(v);
-    if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) plan_flags[1] = std::atoi(v);
-    for (int k = 0; k < kStreams; ++k) {
+    // Compute streams: one for short-chain steps, kLongStreamsDefault for long-chain ones
+    // (HB_SERVER_LONG_STREAMS overrides, up to kStreams - 1).  Every stream may take one of
+    // the process's hardware queues (HIP's default is four, and the application's own
+    // default stream holds one once used); streams sharing a queue wait behind each
+    // other's kernels, and a copy stream sharing one with a compute stream stalls every
+    // request behind multi-millisecond chains.  So by default the loop keeps to three
+    // streams (copy, short, long) and the plans of its steps keep no side stream: plain
+    // persistent-kernel plans, eager launches.  HB_SERVER_LONG_PLAN_FLAGS sets the
+    // long-chain plans' flags (e.g. HB_PLAN_LONG_INLINE: their longest chains rounds-only,
+    // before the bulk; 0: beside it, on a side stream, for processes with a queue to
+    // spare), HB_SERVER_PLAN_FLAGS every plan's.
+    int n_long = kLongStreamsDefault;
+    if (const char *v = std::getenv("HB_SERVER_LONG_STREAMS")) n_long = std::max(1, std::min(kStreams - 1, std::atoi(v)));
+    s->n_streams = 1 + n_long;
+    int plan_flags[kStreams];
+    std::fill(plan_flags, plan_flags + kStreams, int(HB_PLAN_NO_LONG));
+    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) std::fill(plan_flags, plan_flags + kStreams, std::atoi(v));
+    if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) std::fill(plan_flags + 1, plan_flags + kStreams, std::atoi(v));
+    for (int k = 0; k < s->n_streams; ++k) {
         if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: stream", e);
         int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags[k]);

@@ -20,7 +20,7 @@ LIB_PATH = PKG / "libhb.so"
 HEADER = PKG.parent / "include" / "hb.h"
 
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_EHIP, HB_EBUDGET, HB_EBUSY = 0, -1, -2, -3, -4, -5
-PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT, PLAN_NO_LONG = 1, 2, 4, 8
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT, PLAN_NO_LONG, PLAN_LONG_INLINE = 1, 2, 4, 8, 16
 ALGO_IDS = {"md5": MD5, "sha1": SHA1, "sm3": SM3}
 
 _vp = ctypes.c_void_p

@@ -206,7 +206,8 @@ def test_long_chain_direct_cap(hb, monkeypatch):
 def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
     """Messages above the block threshold run as rounds-only chains from precomputed
     schedule words; with a tiny scratch only some of them fit and the rest run as direct
-    chains.  Every digest must match the oracle either way."""
+    chains; the long-chain kernel runs beside the bulk on a side stream, or before it on
+    the run's own stream.  Every digest must match the oracle either way."""
     monkeypatch.setenv("HB_LONG_SCRATCH_MB", scratch_mb)
     monkeypatch.setenv("HB_LONG_MIN_BLOCKS", min_blocks)
     rng = np.random.default_rng(int(min_blocks))
@@ -219,7 +220,7 @@ def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
     algos = rng.integers(0, 3, size=n).astype(np.uint8)
     print(f"case long path scratch={scratch_mb} min_blocks={min_blocks}", flush=True)
     want = oracle.hash_batch(algos, msgs, offs, lens)
-    for flags in (hb.PLAN_GRAPH, 0):
+    for flags in (hb.PLAN_GRAPH, 0, hb.PLAN_GRAPH | hb.PLAN_LONG_INLINE, hb.PLAN_LONG_INLINE):
         plan = hb.Plan(n, flags=flags)
         got = plan.run(msgs, offs, lens, algos=algos).cpu().numpy()
         assert_same(got, want, f"long path flags={flags}")
