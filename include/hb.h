@@ -145,8 +145,8 @@ enum {
     HB_PLAN_AUTOTUNE = 2,   /* time the kernel variants on first use and cache the choice */
     HB_PLAN_NO_SORT = 4,    /* skip bucketing: lanes take messages in index order */
     HB_PLAN_NO_LONG = 8,    /* no separate long-chain path (see hb_plan_create) */
-    HB_PLAN_LONG_INLINE = 16 /* long-chain kernel on the run's stream, before the bulk: no
-                                side stream (and no bulk sizing) */
+    HB_PLAN_LONG_INLINE = 16 /* long-chain work and bulk in one launch on the run's stream:
+                                no side stream */
 };
 
 /*
@@ -161,11 +161,12 @@ enum {
  * those the scratch cannot hold run there as ordinary chains, at most one wave per SIMD
  * (the longest by blocks x ops per block), and when the longest chain dwarfs the rest the
  * bulk kernel runs on only as many waves as finish its work in 1/HB_BULK_MARGIN (default
- * 4; 0 = all waves) of that chain's time.  With HB_PLAN_LONG_INLINE the long-chain
- * kernel runs on the run's own stream before the bulk kernel, which then uses all its
- * waves: no side stream, for callers that keep several plans busy on streams of their own
- * and have no hardware queue to spare for each.  Returns HB_ENOMEM if the workspace cannot
- * be allocated.
+ * 4; 0 = all waves) of that chain's time.  With HB_PLAN_LONG_INLINE the long-chain work
+ * and the bulk run in one launch on the run's own stream (the long chains' workgroups
+ * first), with the same concurrency and no side stream, for callers that keep several
+ * plans busy on streams of their own and have no hardware queue to spare for each; that
+ * launch takes the long-chain kernel's register budget, so its bulk waves run at lower
+ * occupancy.  Returns HB_ENOMEM if the workspace cannot be allocated.
  */
 int hb_plan_create(hb_plan **plan, uint64_t max_n, int flags);
 
@@ -265,13 +266,15 @@ typedef struct hb_server hb_server;
  * limits hold; staging threads pack each admitted request's bytes into pinned memory and
  * copy them into the device on one copy stream; staged requests are batched into hashing
  * steps, requests holding a long chain apart from the rest, each kind on its own compute
- * stream: three streams in all, since streams beyond the process's hardware queues share
- * them and wait behind each other's kernels.  Environment: HB_SERVER_STAGERS staging
+ * stream, long-chain steps with the plan's long-chain path in one launch: three streams
+ * in all, since streams beyond the process's hardware queues share them and wait behind
+ * each other's kernels.  Environment: HB_SERVER_STAGERS staging
  * threads (default 4); HB_SERVER_LONG_STREAMS long-chain streams (default 1; more only
  * help with more hardware queues than HIP's default four); HB_SERVER_LONG_PLAN_FLAGS the
- * long-chain steps' plan flags (default HB_PLAN_NO_LONG; HB_PLAN_LONG_INLINE or 0 give
- * them the long-chain path of hb_plan_create, 0 with a side stream); HB_SERVER_COPY=kernel
- * copies payload by kernel from the rings' device mapping, not the copy engine.  A request arriving while others run starts as soon as memory and a slot free up,
+ * long-chain steps' plan flags (default HB_PLAN_LONG_INLINE: the long-chain path of
+ * hb_plan_create in one launch; 0: with a side stream; HB_PLAN_NO_LONG: none);
+ * HB_SERVER_COPY=kernel copies payload by kernel from the rings' device mapping, not the
+ * copy engine.  A request arriving while others run starts as soon as memory and a slot free up,
  * and its work overlaps theirs on the device.  Returns HB_EINVAL for a null server pointer,
  * a budget below 256 bytes or max_slots <= 0, HB_ENOMEM if the device arena or pinned
  * buffers cannot be allocated, HB_EHIP for other runtime failures.

@@ -557,11 +557,10 @@ __global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
 // scratch could not hold, so no long chain shares the persistent kernel's issue slots at
 // ordinary priority.
 template <int SCHED>
-__global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
+__device__ __forceinline__ void long_lane(const PlanWs &ws, uint32_t g)
 {
     const PlanDesc d = *ws.desc;
     const PlanMeta m = *ws.meta;
-    const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t wave_first = g & ~63u;
     if (g >= ws.max_long_waves * 64u) {
         // direct chains: the long messages the scratch could not hold
@@ -613,6 +612,12 @@ __global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
     __builtin_amdgcn_s_setprio(0);
 }
 
+template <int SCHED>
+__global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
+{
+    long_lane<SCHED>(ws, blockIdx.x * kThreads + threadIdx.x);
+}
+
 template <int A, int PF>
 __device__ __forceinline__ void hash_lane(const PlanDesc &d, uint32_t idx)
 {
@@ -630,13 +635,13 @@ __device__ __forceinline__ void hash_lane(const PlanDesc &d, uint32_t idx)
 // wave priority so the longest chains keep their issue slots.  PF = 1 prefetches the next
 // block of SHA-1 / SM3 messages (MD5 already reads two blocks per burst).
 template <int PF>
-__global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
+__device__ __forceinline__ void persistent_wave(const PlanWs &ws, uint32_t block, uint32_t nblocks)
 {
     const PlanDesc d = *ws.desc;
     const PlanMeta *mp = ws.meta;
     const uint32_t total = mp->seg_item[3];
     const uint32_t per_item = 64u * uint32_t(d.mpl);
-    const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
+    const uint64_t waves = uint64_t(nblocks) * (kThreads / 64);
     const uint64_t share = mp->total_cost / (waves ? waves : 1);
     const uint32_t lane = __lane_id();
     uint32_t bulk = mp->bulk_waves;
@@ -652,7 +657,7 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
             bulk = uint32_t(min<uint64_t>(max<uint64_t>(w, kMinBulkWaves), 0xffffffffull));
         }
     }
-    if (blockIdx.x * (kThreads / 64u) + threadIdx.x / 64u >= bulk) return;  // surplus wave
+    if (block * (kThreads / 64u) + threadIdx.x / 64u >= bulk) return;  // surplus wave
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&ws.meta->queue, 1u);
@@ -680,6 +685,22 @@ __global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
         }
     }
     __builtin_amdgcn_s_setprio(0);
+}
+
+template <int PF>
+__global__ __launch_bounds__(kThreads) void k_hash_persistent(PlanWs ws)
+{
+    persistent_wave<PF>(ws, blockIdx.x, gridDim.x);
+}
+
+// The long-chain kernel and the persistent kernel in one launch: workgroups below
+// long_blocks run the long chains (dispatched first), the rest the bulk.  Same work and
+// concurrency as the two kernels on two streams, without a second stream.
+template <int SCHED, int PF>
+__global__ __launch_bounds__(kThreads) void k_hash_fused(PlanWs ws, uint32_t long_blocks)
+{
+    if (blockIdx.x < long_blocks) long_lane<SCHED>(ws, blockIdx.x * kThreads + threadIdx.x);
+    else persistent_wave<PF>(ws, blockIdx.x - long_blocks, gridDim.x - long_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -831,13 +852,20 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         if (p->long_sched) hipLaunchKernelGGL(k_sched, dim3(g), dim3(kThreads), 0, s, ws);
     }
     if (ev.first) hipEventRecord(ev.first, s);
-    const bool inline_long = p->long_on && !p->side;
-    if (inline_long) {
-        // no side stream: the long chains run first, then the bulk with all its waves
-        const int long_blocks =
-            int((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
-        if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, s, ws);
-        else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, s, ws);
+    const bool fused = p->long_on && !p->side;
+    if (fused) {
+        // no side stream: long chains and bulk in one launch, the chains' workgroups first
+        const uint32_t long_blocks =
+            uint32_t((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
+        const dim3 grid{long_blocks + uint32_t(hash_blocks), 1, 1};
+        if (p->long_sched && p->variant == 1)
+            hipLaunchKernelGGL((k_hash_fused<1, 1>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+        else if (p->long_sched)
+            hipLaunchKernelGGL((k_hash_fused<1, 0>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+        else if (p->variant == 1)
+            hipLaunchKernelGGL((k_hash_fused<0, 1>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+        else
+            hipLaunchKernelGGL((k_hash_fused<0, 0>), grid, dim3(kThreads), 0, s, ws, long_blocks);
     } else if (p->long_on) {
         // fork: the long chains start first on the side stream and run beside the bulk
         hipEventRecord(p->ev_fork, s);
@@ -848,11 +876,11 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         hipEventRecord(p->ev_join, p->side);
     }
-    if (p->variant == 1)
-        hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
-    else
-        hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
-    if (p->long_on && !inline_long) hipStreamWaitEvent(s, p->ev_join, 0);  // join
+    if (!fused) {
+        if (p->variant == 1) hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+        else hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+    }
+    if (p->long_on && !fused) hipStreamWaitEvent(s, p->ev_join, 0);  // join
     if (ev.first) {
         hipEventRecord(ev.second, s);
         p->ev_pending.push_back(ev);
@@ -1060,8 +1088,7 @@ int hb_plan_run(hb_plan *p, const uint8_t *algos, int algo, const uint8_t *messa
     d.algo = algos ? 0 : algo;
     d.sort = (p->flags & HB_PLAN_NO_SORT) ? 0 : 1;
     d.long_min_key = (p->long_on && d.sort) ? p->long_min_key : 0;
-    // no bulk sizing when the long chains run before the bulk instead of beside it
-    d.bulk_margin = (p->long_on && !p->side) ? 0 : p->bulk_margin;
+    d.bulk_margin = p->bulk_margin;
     if ((p->flags & HB_PLAN_AUTOTUNE) && !p->tuned) {
         d.mpl = p->mpl;
         const int mask = algos ? 7 : (1 << algo);

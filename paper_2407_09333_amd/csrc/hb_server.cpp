@@ -551,17 +551,20 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     // the process's hardware queues (HIP's default is four, and the application's own
     // default stream holds one once used); streams sharing a queue wait behind each
     // other's kernels, and a copy stream sharing one with a compute stream stalls every
-    // request behind multi-millisecond chains.  So by default the loop keeps to three
-    // streams (copy, short, long) and the plans of its steps keep no side stream: plain
-    // persistent-kernel plans, eager launches.  HB_SERVER_LONG_PLAN_FLAGS sets the
-    // long-chain plans' flags (e.g. HB_PLAN_LONG_INLINE: their longest chains rounds-only,
-    // before the bulk; 0: beside it, on a side stream, for processes with a queue to
-    // spare), HB_SERVER_PLAN_FLAGS every plan's.
+    // request behind multi-millisecond chains.  So the loop keeps to three streams (copy,
+    // short, long) and its plans take no side stream: short-chain steps are plain
+    // persistent-kernel plans (nothing in them reaches the long-chain threshold);
+    // long-chain steps take the long-chain path in one launch with the bulk
+    // (HB_PLAN_LONG_INLINE), so their longest chains run rounds-only from precomputed
+    // schedule words beside the bulk -- the chain is what such a step's latency is.
+    // HB_SERVER_LONG_PLAN_FLAGS sets the long-chain plans' flags, HB_SERVER_PLAN_FLAGS
+    // every plan's.  Plans launch eagerly.
     int n_long = kLongStreamsDefault;
     if (const char *v = std::getenv("HB_SERVER_LONG_STREAMS")) n_long = std::max(1, std::min(kStreams - 1, std::atoi(v)));
     s->n_streams = 1 + n_long;
     int plan_flags[kStreams];
-    std::fill(plan_flags, plan_flags + kStreams, int(HB_PLAN_NO_LONG));
+    plan_flags[0] = HB_PLAN_NO_LONG;
+    std::fill(plan_flags + 1, plan_flags + kStreams, int(HB_PLAN_LONG_INLINE));
     if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) std::fill(plan_flags, plan_flags + kStreams, std::atoi(v));
     if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) std::fill(plan_flags + 1, plan_flags + kStreams, std::atoi(v));
     for (int k = 0; k < s->n_streams; ++k) {

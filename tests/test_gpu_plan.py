@@ -185,7 +185,8 @@ def test_long_chain_direct_cap(hb, monkeypatch):
     """More long candidates than direct-chain waves (one per SIMD): a cost threshold
     across the three algorithms picks the longest chains for the long-chain kernel, the
     rest stay in the persistent kernel.  A 1 MiB scratch holds no wave of them, so every
-    chosen one runs as a direct chain."""
+    chosen one runs as a direct chain; on a side stream or in one launch with the bulk,
+    with either persistent-kernel variant."""
     monkeypatch.setenv("HB_LONG_SCRATCH_MB", "1")
     monkeypatch.setenv("HB_LONG_MIN_BLOCKS", "2")
     rng = np.random.default_rng(41)
@@ -197,9 +198,12 @@ def test_long_chain_direct_cap(hb, monkeypatch):
     algos = rng.integers(0, 3, size=n).astype(np.uint8)
     print("case long path direct cap", flush=True)
     want = oracle.hash_batch(algos, msgs, offs, lens)
-    plan = hb.Plan(n, flags=hb.PLAN_GRAPH)
-    assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "direct cap")
-    plan.close()
+    for flags in (hb.PLAN_GRAPH, hb.PLAN_GRAPH | hb.PLAN_LONG_INLINE):
+        for var in (0, 1):
+            plan = hb.Plan(n, flags=flags)
+            plan.set_config(waves_per_cu=16, msgs_per_lane=1, variant=var)
+            assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, f"direct cap {flags} {var}")
+            plan.close()
 
 
 @pytest.mark.parametrize("scratch_mb,min_blocks", [("1", "256"), ("512", "2"), ("1024", "16")])
@@ -225,6 +229,10 @@ def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
         got = plan.run(msgs, offs, lens, algos=algos).cpu().numpy()
         assert_same(got, want, f"long path flags={flags}")
         plan.close()
+    plan = hb.Plan(n, flags=hb.PLAN_LONG_INLINE)
+    plan.set_config(waves_per_cu=16, msgs_per_lane=2, variant=1)
+    assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "one launch, variant 1")
+    plan.close()
     plan = hb.Plan(n, flags=hb.PLAN_NO_LONG)
     assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "no long path")
     plan.close()
