@@ -166,7 +166,7 @@ struct hb_server {
     std::mutex copy_mu;             // orders the copy marks' records on copy_in
     uint64_t copy_seq = 0;          // (under copy_mu)
     hipStream_t compute[kStreams] = {};
-    hb_plan *plan[kStreams] = {};
+    hb_plan *plan[kStreams][2] = {}; // per stream, by the class of the step it runs
     uint8_t *h_meta[kStreams] = {}; // pinned, coherent: offsets | lengths | ids | digests
     uint8_t *m_meta[kStreams] = {}; // the same buffer through its device mapping
     uint8_t *d_meta[kStreams] = {};
@@ -356,7 +356,7 @@ int launch_step(hb_server *s, int k, int c)
     if (e != hipSuccess) return fail(hip_error(e, "hb_server: step metadata"));
     st->begin = take_event(s);
     if (!st->begin || hipEventRecord(st->begin, cs) != hipSuccess) return fail(set_error(HB_EHIP, "hb_server: step event"));
-    int rc = hb_plan_run(s->plan[k], st->mixed ? di : nullptr, st->algo, s->d_arena, dof, dl, n, dd, cs);
+    int rc = hb_plan_run(s->plan[k][c], st->mixed ? di : nullptr, st->algo, s->d_arena, dof, dl, n, dd, cs);
     if (rc != HB_OK) return fail(rc);
     e = launch_copy(mm + kMaxStepN * 17, dd, n * stride, cs);
     if (e != hipSuccess) return fail(hip_error(e, "hb_server: digest copy"));
@@ -552,9 +552,10 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     // default stream holds one once used); streams sharing a queue wait behind each
     // other's kernels, and a copy stream sharing one with a compute stream stalls every
     // request behind multi-millisecond chains.  So the loop keeps to three streams (copy,
-    // short, long) and its plans take no side stream: short-chain steps are plain
-    // persistent-kernel plans (nothing in them reaches the long-chain threshold);
-    // long-chain steps take the long-chain path in one launch with the bulk
+    // short, long) and its plans take no side stream.  Each stream keeps a plan per step
+    // class, since an idle stream also runs the other class's steps: short-chain steps
+    // are plain persistent-kernel plans (nothing in them reaches the long-chain
+    // threshold); long-chain steps take the long-chain path in one launch with the bulk
     // (HB_PLAN_LONG_INLINE), so their longest chains run rounds-only from precomputed
     // schedule words beside the bulk -- the chain is what such a step's latency is.
     // HB_SERVER_LONG_PLAN_FLAGS sets the long-chain plans' flags, HB_SERVER_PLAN_FLAGS
@@ -562,16 +563,16 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     int n_long = kLongStreamsDefault;
     if (const char *v = std::getenv("HB_SERVER_LONG_STREAMS")) n_long = std::max(1, std::min(kStreams - 1, std::atoi(v)));
     s->n_streams = 1 + n_long;
-    int plan_flags[kStreams];
-    plan_flags[0] = HB_PLAN_NO_LONG;
-    std::fill(plan_flags + 1, plan_flags + kStreams, int(HB_PLAN_LONG_INLINE));
-    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) std::fill(plan_flags, plan_flags + kStreams, std::atoi(v));
-    if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) std::fill(plan_flags + 1, plan_flags + kStreams, std::atoi(v));
+    int plan_flags[2] = {HB_PLAN_NO_LONG, HB_PLAN_LONG_INLINE};  // by step class
+    if (const char *v = std::getenv("HB_SERVER_PLAN_FLAGS")) plan_flags[0] = plan_flags[1] = std::atoi(v);
+    if (const char *v = std::getenv("HB_SERVER_LONG_PLAN_FLAGS")) plan_flags[1] = std::atoi(v);
     for (int k = 0; k < s->n_streams; ++k) {
         if ((e = hipStreamCreateWithFlags(&s->compute[k], hipStreamNonBlocking)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: stream", e);
-        int rc = hb_plan_create(&s->plan[k], kMaxStepN, plan_flags[k]);
-        if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
+        for (int c = 0; c < 2; ++c) {
+            int rc = hb_plan_create(&s->plan[k][c], kMaxStepN, plan_flags[c]);
+            if (rc != HB_OK) return fail(rc, "hb_server_create: plan", hipSuccess);
+        }
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_meta[k]), meta_bytes(kMaxStepN),
                                hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: pinned step buffers", hipSuccess);
@@ -730,7 +731,8 @@ void hb_server_destroy(hb_server *s)
     }
     for (int k = 0; k < kStreams; ++k) {
         if (s->compute[k]) hipStreamSynchronize(s->compute[k]);
-        if (s->plan[k]) hb_plan_destroy(s->plan[k]);
+        for (hb_plan *pl : s->plan[k])
+            if (pl) hb_plan_destroy(pl);
         if (s->h_meta[k]) hipHostFree(s->h_meta[k]);
         if (s->d_meta[k]) hipFree(s->d_meta[k]);
         if (s->compute[k]) hipStreamDestroy(s->compute[k]);
