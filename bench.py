@@ -659,6 +659,7 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
               file=sys.stderr, flush=True)
     peak = srv.stats()["peak_bytes"]
     srv.close()
+    overload = bench_serve_overload(pool)
     head = runs[0]  # the fixed offered rate
     return {
         "workload": "Poisson arrivals; 1..10,000 messages per request (log-uniform), algorithm uniform, "
@@ -669,8 +670,39 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
                     "other sweep entries are fractions of the burst capacity C, which varies run to run",
         "offered_req_per_s": head["offered_req_per_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "p999_ms": head["p999_ms"], "achieved_GBps": head["achieved_GBps"],
-        "sweep": runs, "peak_resident_bytes": peak,
+        "sweep": runs, "peak_resident_bytes": peak, "overload": overload,
     }
+
+
+def bench_serve_overload(pool, n_req=160_000, budget=64 << 30):
+    """Overload burst: about 140 GB of requests (the serving distribution, the pool cycled)
+    submitted at once against the 64 GiB device budget, with slots enough that the budget
+    is what admission waits on; every request completes, and the resident payload never
+    exceeds the budget."""
+    from paper_2407_09333_amd import hb
+
+    srv = hb.Server(hbm_budget_bytes=budget, max_slots=1 << 17)
+    t0 = srv.now()
+    tickets, payload = [], 0
+    for k in range(n_req):
+        r = pool[k % len(pool)]
+        tickets.append(srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos))
+        payload += int(r.lengths.sum())
+    t_sub = srv.now() - t0
+    for t in tickets:
+        srv.wait(t)
+    wall = srv.now() - t0
+    st = srv.stats()
+    srv.close()
+    res = {"requests": n_req, "payload_bytes": payload, "budget_bytes": budget, "submitted_s": round(t_sub, 3),
+           "wall_s": round(wall, 3), "GBps": round(payload / wall / 1e9, 3), "completed": st["completed"],
+           "admission_stalls": st["stalls"], "peak_resident_bytes": st["peak_bytes"],
+           "peak_within_budget": st["peak_bytes"] <= budget}
+    print(f"bench: serving overload {payload / 1e9:.1f} GB against a {budget >> 30} GiB budget: "
+          f"submitted in {t_sub:.2f} s, done in {wall:.2f} s, {st['stalls']} admission stalls, "
+          f"peak resident {st['peak_bytes'] / 2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+    return res
 
 def main():
     args = parse()
