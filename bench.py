@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--only-headline", action="store_true",
                    help="skip the batched, mixed and serving sections of the default run")
     p.add_argument("--serve-seconds", type=float, default=15.0)
+    p.add_argument("--no-overload", action="store_true", help="skip the serving overload burst")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     p.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -659,7 +660,7 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
               file=sys.stderr, flush=True)
     peak = srv.stats()["peak_bytes"]
     srv.close()
-    overload = bench_serve_overload(pool)
+    overload = None if getattr(args, "no_overload", False) else bench_serve_overload(pool)
     head = runs[0]  # the fixed offered rate
     return {
         "workload": "Poisson arrivals; 1..10,000 messages per request (log-uniform), algorithm uniform, "

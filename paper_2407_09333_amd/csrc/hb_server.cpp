@@ -53,6 +53,7 @@ constexpr int kStagersDefault = 4;             // staging threads (HB_SERVER_STA
 constexpr uint64_t kPiece = 16ull << 20;       // largest single staging copy
 constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per staging thread
 constexpr size_t kMaxGroup = 256;              // requests staged together at most
+constexpr size_t kMaxInflight = 64;            // copies in flight per staging thread at most
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -119,13 +120,16 @@ struct Stager {
     std::vector<hipEvent_t> spare;   // events of retired segments
 
     // Reserve `want` (<= kRing) contiguous bytes; returns their offset or kRing on error.
+    // Also keeps fewer than kMaxInflight copies in flight: a ring of small requests would
+    // otherwise queue thousands of transfers, and their events, on the copy stream.
     uint64_t reserve(uint64_t want)
     {
         head = (head + 255) & ~uint64_t(255);  // copies start 256-byte aligned
         if (head + want > kRing) head = 0;
         while (!inflight.empty()) {
             const Segment &o = inflight.front();
-            if (o.end <= head || o.begin >= head + want) break;  // oldest does not overlap: none does
+            const bool overlaps = !(o.end <= head || o.begin >= head + want);  // only the oldest can
+            if (!overlaps && inflight.size() < kMaxInflight) break;
             if (hipEventSynchronize(o.copied) != hipSuccess) return kRing;
             spare.push_back(o.copied);
             inflight.pop_front();
