@@ -643,6 +643,7 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
                         tm["exec_begin"] - tm["launch"], tm["exec_end"] - tm["exec_begin"],
                         tm["done"] - tm["exec_end"])
             done_max = max(done_max, tm["done"])
+            srv.release(t)
         s1 = srv.stats()
         runs.append({"load_fraction": frac, "offered_req_per_s": round(rate, 1), "requests": n_req,
                      "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
@@ -692,6 +693,7 @@ def bench_serve_overload(pool, n_req=160_000, budget=64 << 30):
     t_sub = srv.now() - t0
     for t in tickets:
         srv.wait(t)
+        srv.release(t)
     wall = srv.now() - t0
     st = srv.stats()
     srv.close()

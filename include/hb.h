@@ -37,7 +37,8 @@ extern "C" {
 #endif
 
 enum { HB_MD5 = 0, HB_SHA1 = 1, HB_SM3 = 2 };
-enum { HB_OK = 0, HB_EINVAL = -1, HB_ENOMEM = -2, HB_EHIP = -3, HB_EBUDGET = -4, HB_EBUSY = -5 };
+enum { HB_OK = 0, HB_EINVAL = -1, HB_ENOMEM = -2, HB_EHIP = -3, HB_EBUDGET = -4, HB_EBUSY = -5,
+       HB_ECANCELED = -6 };
 
 /* Digest size in bytes of algo (16, 20 or 32); 0 for an unknown id. */
 size_t hb_digest_size(int algo);
@@ -295,6 +296,16 @@ int hb_server_submit(hb_server *server, int algo_or_mixed, const uint8_t *algos,
 
 /* Non-blocking completion check: *done = 1 when finished, with its status in *status. */
 int hb_server_poll(hb_server *server, uint64_t ticket, int *done, int *status);
+
+/* Cancel a request that has not been admitted yet: it leaves the queue and finishes with
+ * status HB_ECANCELED (its digest slots untouched).  HB_EBUSY once it has been admitted
+ * (it then runs to completion), HB_EINVAL for an unknown ticket. */
+int hb_server_cancel(hb_server *server, uint64_t ticket);
+
+/* Drop the record of a finished request (after its status, times or trace have been
+ * read); the ticket is unknown afterwards.  A server keeps every request's record until
+ * this call or hb_server_destroy.  HB_EBUSY if the request has not finished. */
+int hb_server_release(hb_server *server, uint64_t ticket);
 
 /* Block until the request completes (or timeout_ms elapses, -1 = forever: HB_EBUSY on
  * timeout); *status receives its status. */

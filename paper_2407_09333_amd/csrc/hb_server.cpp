@@ -653,6 +653,38 @@ int hb_server_poll(hb_server *s, uint64_t ticket, int *done, int *status)
     return HB_OK;
 }
 
+int hb_server_cancel(hb_server *s, uint64_t ticket)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_cancel: null server");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_cancel: unknown ticket");
+        Req *r = it->second.get();
+        if (r->st != St::Pending) return set_error(HB_EBUSY, "hb_server_cancel: request already admitted");
+        auto q = std::find(s->pending.begin(), s->pending.end(), r);
+        if (q == s->pending.end()) return set_error(HB_EBUSY, "hb_server_cancel: request already admitted");
+        s->pending.erase(q);
+        r->status = HB_ECANCELED;
+        r->t_admit = r->t_h2d = r->t_done = s->now();
+        r->st = St::Done;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();  // the next request may now be admissible
+    return HB_OK;
+}
+
+int hb_server_release(hb_server *s, uint64_t ticket)
+{
+    if (!s) return set_error(HB_EINVAL, "hb_server_release: null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_release: unknown ticket");
+    if (it->second->st != St::Done) return set_error(HB_EBUSY, "hb_server_release: request not finished");
+    s->all.erase(it);
+    return HB_OK;
+}
+
 int hb_server_wait(hb_server *s, uint64_t ticket, int64_t timeout_ms, int *status)
 {
     if (!s) return set_error(HB_EINVAL, "hb_server_wait: null server");

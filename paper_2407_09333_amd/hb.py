@@ -19,7 +19,7 @@ PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "libhb.so"
 HEADER = PKG.parent / "include" / "hb.h"
 
-HB_OK, HB_EINVAL, HB_ENOMEM, HB_EHIP, HB_EBUDGET, HB_EBUSY = 0, -1, -2, -3, -4, -5
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_EHIP, HB_EBUDGET, HB_EBUSY, HB_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_NO_SORT, PLAN_NO_LONG, PLAN_LONG_INLINE = 1, 2, 4, 8, 16
 ALGO_IDS = {"md5": MD5, "sha1": SHA1, "sm3": SM3}
 
@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(_u64)]
             L.hb_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(_i)]
             L.hb_server_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(_i)]
+            L.hb_server_cancel.argtypes = [_vp, _u64]
+            L.hb_server_release.argtypes = [_vp, _u64]
             L.hb_server_times.argtypes = [_vp, _u64] + [ctypes.POINTER(ctypes.c_double)] * 4
             L.hb_server_trace.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_double), _i]
             L.hb_server_stats.argtypes = [_vp] + [ctypes.POINTER(_u64)] * 4
@@ -363,11 +365,26 @@ class Server:
         return bool(d.value), st.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> np.ndarray:
+        """Digests of a finished request; raises HBError with the request's status if it
+        failed or was cancelled (HB_EBUSY on timeout)."""
         st = _i()
         check(lib().hb_server_wait(self._h, ticket, timeout_ms, ctypes.byref(st)))
-        check(st.value)
         msgs, offs, lens, al, out = self._live.pop(ticket)
+        check(st.value)
         return out[: offs.size]
+
+    def cancel(self, ticket: int) -> bool:
+        """Cancel a request not yet admitted (True); False once it has been admitted."""
+        rc = lib().hb_server_cancel(self._h, ticket)
+        if rc == HB_EBUSY:
+            return False
+        check(rc)
+        return True
+
+    def release(self, ticket: int):
+        """Drop a finished request's record (its status, times and trace)."""
+        check(lib().hb_server_release(self._h, ticket))
+        self._live.pop(ticket, None)
 
     def times(self, ticket: int) -> dict:
         v = [ctypes.c_double() for _ in range(4)]

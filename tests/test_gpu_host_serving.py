@@ -293,3 +293,36 @@ def test_serving_long_chain_steps(hb, monkeypatch, env):
         assert_same(o, _want(r), "serving long chains")
     assert srv.stats()["completed"] == len(reqs)
     srv.close()
+
+
+def test_serving_cancel_and_release(hb):
+    """Requests held back by a small budget can be cancelled while queued: they finish with
+    HB_ECANCELED and their slots untouched; the rest complete bit-exact.  Admitted or
+    finished requests cannot be cancelled; finished ones can be released."""
+    rng = np.random.default_rng(71)
+    reqs = []
+    for r in range(30):
+        lens = rng.integers(2000, 6000, size=200).astype(np.uint64)  # ~0.8 MB each
+        offs = workloads.packed(lens)
+        reqs.append(workloads.Request(0.0, r % 3, None, lens, workloads.host_random_bytes(int(lens.sum()), 500 + r),
+                                      offs))
+    print("case serving cancel/release", flush=True)
+    srv = hb.Server(hbm_budget_bytes=2 << 20, max_slots=2)
+    tickets = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo) for r in reqs]
+    cancelled = {t for t in tickets[10::2] if srv.cancel(t)}
+    assert len(cancelled) >= 5  # the budget holds all but a few requests back
+    for r, t in zip(reqs, tickets):
+        if t in cancelled:
+            with pytest.raises(hb.HBError) as e:
+                srv.wait(t, timeout_ms=60_000)
+            assert e.value.status == hb.HB_ECANCELED
+        else:
+            assert_same(srv.wait(t, timeout_ms=60_000), _want(r), "serving after cancels")
+    assert srv.cancel(tickets[0]) is False  # finished: nothing to cancel
+    assert srv.stats()["completed"] == len(reqs) - len(cancelled)
+    for t in tickets:
+        srv.release(t)
+    with pytest.raises(hb.HBError) as e:
+        srv.release(tickets[0])
+    assert e.value.status == hb.HB_EINVAL
+    srv.close()
