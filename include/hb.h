@@ -219,7 +219,9 @@ void hb_plan_destroy(hb_plan *plan);
  * device mapping and writes the digests to pinned memory, with no copy-engine transfer
  * (HB_HOST_ZERO_COPY_MAX, in bytes, overrides the payload limit; 0 turns this off).
  * Blocking: returns when every digest is in digests_out_host.  Allocates device and
- * pinned buffers on first use and keeps them for later calls (per thread).
+ * pinned buffers and its plans on first use and keeps them for later calls (per thread;
+ * a batch holding messages of HB_LONG_MIN_BLOCKS blocks or more adds a plan with the
+ * long-chain path and its scratch); its streams are released at the end of each call.
  */
 int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_t *messages_host,
                     const uint64_t *offsets_host, const uint64_t *lengths_host, uint64_t n,

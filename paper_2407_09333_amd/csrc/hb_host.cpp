@@ -44,9 +44,10 @@ struct HostPipe {
     int device = -1;
     hipStream_t copy = nullptr, compute = nullptr;  // H2D; hashing and the digest write-back
     Slot slot[2];
-    // Two plans: one without the long-chain path (no streams of its own, kept between
-    // calls) and one with it (it owns a side stream, so it is released after each call).
-    // The host sees every length, so it knows which one a batch needs.
+    // Two plans, both kept between calls and neither with a stream of its own: one
+    // without the long-chain path and one with it, in one launch with the bulk (it also
+    // holds the long-chain scratch, HB_LONG_SCRATCH_MB).  The host sees every length, so
+    // it knows which one a batch needs.
     hb_plan *plan = nullptr, *plan_long = nullptr;
     uint64_t plan_n = 0, plan_long_n = 0;
 
@@ -65,7 +66,6 @@ struct HostPipe {
     {
         if (compute) { hipStreamSynchronize(compute); hipStreamDestroy(compute); compute = nullptr; }
         if (copy) { hipStreamSynchronize(copy); hipStreamDestroy(copy); copy = nullptr; }
-        if (plan_long) { hb_plan_destroy(plan_long); plan_long = nullptr; plan_long_n = 0; }
     }
 
     static void release(Slot &s)
@@ -285,7 +285,7 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
     if (!plan || plan_n < largest_n) {
         if (plan) hb_plan_destroy(plan);
         plan = nullptr;
-        int rc = hb_plan_create(&plan, std::max<uint64_t>(largest_n, 4096), want_long ? 0 : HB_PLAN_NO_LONG);
+        int rc = hb_plan_create(&plan, std::max<uint64_t>(largest_n, 4096), want_long ? HB_PLAN_LONG_INLINE : HB_PLAN_NO_LONG);
         if (rc != HB_OK) return rc;
         plan_n = std::max<uint64_t>(largest_n, 4096);
     }
@@ -338,9 +338,9 @@ extern "C" int hash_batch_host(const uint8_t *algos_host, int algo, const uint8_
         int r2 = drain(s);
         if (rc == HB_OK) rc = r2;
     }
-    // Release the streams (and the long-chain plan's) between calls: each stream may hold
-    // one of the process's few hardware queues, and idle streams still shift which queue
-    // later streams of the caller (or of a serving loop) share.  Buffers are kept.
+    // Release the streams between calls: each stream may hold one of the process's few
+    // hardware queues, and idle streams still shift which queue later streams of the
+    // caller (or of a serving loop) share.  Buffers and plans are kept.
     P.release_streams();
     return rc;
 }
