@@ -33,6 +33,7 @@
 #include "../../include/hb.h"
 #include "hb_arena.hpp"
 #include "hb_internal.hpp"
+#include "hb_policy.hpp"
 #include "hb_stage.hpp"
 
 namespace hb {
@@ -41,7 +42,6 @@ namespace {
 constexpr int kStreams = 8;                    // compute streams at most: 0 short requests,
                                                // the others long ones
 constexpr int kLongStreamsDefault = 1;
-inline int stream_class(int k) { return k == 0 ? 0 : 1; }
 constexpr uint64_t kLongChain = 128 * 1350;    // a request is "long" if its longest message's
                                                // chain exceeds this many ops (128 SM3 blocks)
 constexpr size_t kMinBatch = 8;                // a step waits for this many staged requests...
@@ -437,53 +437,32 @@ void loop(hb_server *s)
                 s->cv_work.wait_for(g, std::chrono::milliseconds(50));
                 continue;
             }
-            while (!s->pending.empty() && s->slots_used < s->max_slots) {
-                Req *r = s->pending.front();
-                uint64_t off = 0;
-                if (r->payload) {
-                    off = s->arena.alloc(r->payload);
-                    if (off == Arena::kFail) break;
-                }
-                r->arena_off = off;
+            admitted = admit_in_order(s->pending, s->arena, s->slots_used, s->max_slots, [&](Req *r) {
                 r->st = St::Admitted;
                 r->t_admit = s->now();
-                s->slots_used++;
-                s->pending.pop_front();
                 s->to_stage.push_back(r);
-                ++admitted;
-            }
+            });
             if (!s->pending.empty() && !s->pending.front()->stalled) {
                 s->pending.front()->stalled = true;
                 s->stalls++;
             }
             if (s->arena.peak() > s->peak) s->peak = s->arena.peak();
-            // continuous batching: stream 0 serves short requests, the others long ones; a
-            // step is launched when one of its class's streams is idle and either no step is
-            // running, enough requests are staged, or the oldest has waited long enough (one
-            // step per class at a time).  An idle stream whose class has nothing staged takes
-            // the other class's requests while all of that class's streams are busy.
-            const double now = s->now();
-            auto ready = [&](int c) {
-                const std::vector<Req *> &q = s->staged[c];
-                return !q.empty() && (!any_busy || q.size() >= kMinBatch || now - q.front()->t_staged >= kMaxWait);
-            };
-            auto all_busy = [&](int c) {
-                for (int k = 0; k < s->n_streams; ++k)
-                    if (stream_class(k) == c && !s->busy[k]) return false;
-                return true;
-            };
-            bool launched[2] = {false, false};
-            for (int k = 0; k < s->n_streams; ++k) {
-                if (s->busy[k]) continue;
-                const int c = stream_class(k), o = 1 - c;
-                if (!launched[c] && ready(c)) {
-                    launch_cls[k] = c;
-                    launched[c] = true;
-                } else if (s->staged[c].empty() && !launched[o] && all_busy(o) && ready(o)) {
-                    launch_cls[k] = o;
-                    launched[o] = true;
-                }
+            // continuous batching (choose_launches): one step per class at a time, on an
+            // idle stream of its class, once enough requests are staged or the oldest has
+            // waited long enough; an idle stream may take the other class's step
+            LaunchInputs in;
+            bool busy[kStreams];
+            for (int k = 0; k < s->n_streams; ++k) busy[k] = bool(s->busy[k]);
+            in.n_streams = s->n_streams;
+            in.busy = busy;
+            for (int c = 0; c < 2; ++c) {
+                in.staged[c] = s->staged[c].size();
+                in.oldest_staged[c] = s->staged[c].empty() ? 0.0 : s->staged[c].front()->t_staged;
             }
+            in.now = s->now();
+            in.min_batch = kMinBatch;
+            in.max_wait = kMaxWait;
+            choose_launches(in, launch_cls);
         }
         if (admitted) s->cv_stage.notify_all();
         // 2. launch steps on idle compute streams

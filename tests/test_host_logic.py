@@ -1,5 +1,6 @@
-"""Host-side logic that needs no GPU: the serving arena allocator, built with g++ (and
-with the address and undefined-behaviour sanitizers when available)."""
+"""Host-side logic that needs no GPU: the serving loop's arena allocator, staging packer and
+admission / step-launch policy, built with g++ (and with the address and
+undefined-behaviour sanitizers when available)."""
 import shutil
 import subprocess
 from pathlib import Path
@@ -40,3 +41,22 @@ def test_stage_group_packing(tmp_path, sanitize):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "stage ok" in out.stdout
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_serving_policy(tmp_path, sanitize):
+    """The serving loop's admission (arrival order, budget, slots) and step-launch
+    decisions (per class, one step per class, cross-class takeover only when that class's
+    streams are all busy), under a simulated clock with simulated streams: every decision
+    keeps the rules and every request of random open-loop workloads completes."""
+    exe = tmp_path / "policy_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", str(HERE / "cpp" / "policy_check.cpp"), "-o", str(exe)]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "policy ok" in out.stdout
