@@ -25,6 +25,26 @@ from pathlib import Path
 
 import numpy as np
 
+# Hardware queues per process for HIP (GPU_MAX_HW_QUEUES, read once when the runtime
+# starts): --hw-queues, default eight rather than HIP's four, so the serving loop can run
+# two long-chain streams beside its copy and short-chain streams and the process's own
+# default stream without two of them sharing a queue.  Set here, before anything
+# initialises the GPU; the value is reported in the output line.
+HW_QUEUES_DEFAULT = 8
+
+
+def _set_hw_queues(argv):
+    n = HW_QUEUES_DEFAULT
+    for i, a in enumerate(argv):
+        if a == "--hw-queues" and i + 1 < len(argv):
+            n = int(argv[i + 1])
+        elif a.startswith("--hw-queues="):
+            n = int(a.split("=", 1)[1])
+    os.environ["GPU_MAX_HW_QUEUES"] = str(n)
+
+
+_set_hw_queues(sys.argv)
+
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
@@ -52,6 +72,8 @@ def parse():
                    help="skip the batched, mixed and serving sections of the default run")
     p.add_argument("--serve-seconds", type=float, default=15.0)
     p.add_argument("--no-overload", action="store_true", help="skip the serving overload burst")
+    p.add_argument("--hw-queues", type=int, default=HW_QUEUES_DEFAULT,
+                   help="HIP hardware queues for this process (GPU_MAX_HW_QUEUES, at most 32)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     p.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -746,6 +768,7 @@ def main():
         rec = {"paper_workload_digits9": bench_digits9(args)}
     else:
         rec = {"serving": bench_serve(args, seconds=args.serve_seconds)}
+    rec["hip_hw_queues"] = int(os.environ["GPU_MAX_HW_QUEUES"])
     print(json.dumps(rec), flush=True)
 
 

@@ -270,10 +270,12 @@ typedef struct hb_server hb_server;
  * copy them into the device on one copy stream; staged requests are batched into hashing
  * steps, requests holding a long chain apart from the rest, each kind on its own compute
  * stream, long-chain steps with the plan's long-chain path in one launch: three streams
- * in all, since streams beyond the process's hardware queues share them and wait behind
- * each other's kernels.  Environment: HB_SERVER_STAGERS staging
- * threads (default 4); HB_SERVER_LONG_STREAMS long-chain streams (default 1; more only
- * help with more hardware queues than HIP's default four); HB_SERVER_LONG_PLAN_FLAGS the
+ * in all (four with two long-chain streams), since streams beyond the process's hardware
+ * queues share them and wait behind each other's kernels.  Environment: HB_SERVER_STAGERS
+ * staging
+ * threads (default 4); HB_SERVER_LONG_STREAMS long-chain streams (default 1, or 2 when
+ * the process was started with GPU_MAX_HW_QUEUES >= 8: more long-chain streams only help
+ * with more hardware queues than HIP's default four); HB_SERVER_LONG_PLAN_FLAGS the
  * long-chain steps' plan flags (default HB_PLAN_LONG_INLINE: the long-chain path of
  * hb_plan_create in one launch; 0: with a side stream; HB_PLAN_NO_LONG: none);
  * HB_SERVER_COPY=kernel copies payload by kernel from the rings' device mapping, not the

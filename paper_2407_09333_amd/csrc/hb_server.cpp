@@ -529,8 +529,9 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     }
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: stream", e);
-    // Compute streams: one for short-chain steps, kLongStreamsDefault for long-chain ones
-    // (HB_SERVER_LONG_STREAMS overrides, up to kStreams - 1).  Every stream may take one of
+    // Compute streams: one for short-chain steps, kLongStreamsDefault for long-chain ones,
+    // two when the process has eight hardware queues (HB_SERVER_LONG_STREAMS overrides,
+    // up to kStreams - 1).  Every stream may take one of
     // the process's hardware queues (HIP's default is four, and the application's own
     // default stream holds one once used); streams sharing a queue wait behind each
     // other's kernels, and a copy stream sharing one with a compute stream stalls every
@@ -544,6 +545,9 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     // HB_SERVER_LONG_PLAN_FLAGS sets the long-chain plans' flags, HB_SERVER_PLAN_FLAGS
     // every plan's.  Plans launch eagerly.
     int n_long = kLongStreamsDefault;
+    // a process started with GPU_MAX_HW_QUEUES >= 8 (HIP's hardware queues per process)
+    // has queues for a second long-chain stream
+    if (const char *v = std::getenv("GPU_MAX_HW_QUEUES"); v && std::atoi(v) >= 8) n_long = 2;
     if (const char *v = std::getenv("HB_SERVER_LONG_STREAMS")) n_long = std::max(1, std::min(kStreams - 1, std::atoi(v)));
     s->n_streams = 1 + n_long;
     int plan_flags[2] = {HB_PLAN_NO_LONG, HB_PLAN_LONG_INLINE};  // by step class
