@@ -278,6 +278,7 @@ typedef struct hb_server hb_server;
  * with more hardware queues than HIP's default four); HB_SERVER_LONG_PLAN_FLAGS the
  * long-chain steps' plan flags (default HB_PLAN_LONG_INLINE: the long-chain path of
  * hb_plan_create in one launch; 0: with a side stream; HB_PLAN_NO_LONG: none);
+ * HB_SERVER_COPY_STREAMS copy streams (default 1, or 2 with GPU_MAX_HW_QUEUES >= 8);
  * HB_SERVER_COPY=kernel copies payload by kernel from the rings' device mapping, not the
  * copy engine.  A request arriving while others run starts as soon as memory and a slot free up,
  * and its work overlaps theirs on the device.  Returns HB_EINVAL for a null server pointer,

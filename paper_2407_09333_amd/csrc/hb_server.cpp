@@ -54,6 +54,7 @@ constexpr uint64_t kPiece = 16ull << 20;       // largest single staging copy
 constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per staging thread
 constexpr size_t kMaxGroup = 256;              // requests staged together at most
 constexpr size_t kMaxInflight = 64;            // copies in flight per staging thread at most
+constexpr int kCopyStreams = 2;                // copy streams at most
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -61,7 +62,8 @@ enum class St { Pending, Admitted, Launched, Done };
 // the group's last piece, shared by the group's requests.
 struct CopyMark {
     hipEvent_t ev = nullptr;
-    uint64_t seq = 0;   // position among the marks on the copy stream
+    int cs = 0;         // copy stream it was recorded on
+    uint64_t seq = 0;   // position among the marks on that copy stream
     double t = -1;      // host time of ev, once read
     CopyMark() = default;
     CopyMark(const CopyMark &) = delete;
@@ -115,6 +117,7 @@ struct Stager {
     std::thread thr;
     uint8_t *buf = nullptr;          // kRing pinned bytes
     uint8_t *dbuf = nullptr;         // their device mapping (kernel copies)
+    int copy_stream = 0;             // index of the copy stream its transfers go on
     uint64_t head = 0;               // next free byte
     std::deque<Segment> inflight;    // in ring order, oldest first
     std::vector<hipEvent_t> spare;   // events of retired segments
@@ -165,10 +168,11 @@ struct hb_server {
     Arena arena;
     uint8_t *d_arena = nullptr;
     std::vector<hipEvent_t> ev_pool;
-    hipStream_t copy_in = nullptr;  // all staging copies (one hardware queue for the copies)
+    hipStream_t copy_in[kCopyStreams] = {};  // staging copies; staging thread w uses w % n_copy
+    int n_copy = 1;
     bool copy_kernel = false;       // payload copies by kernel from the rings' device mapping
-    std::mutex copy_mu;             // orders the copy marks' records on copy_in
-    uint64_t copy_seq = 0;          // (under copy_mu)
+    std::mutex copy_mu[kCopyStreams];  // orders the copy marks' records on each copy stream
+    uint64_t copy_seq[kCopyStreams] = {};  // (under copy_mu)
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams][2] = {}; // per stream, by the class of the step it runs
     uint8_t *h_meta[kStreams] = {}; // pinned, coherent: offsets | lengths | ids | digests
@@ -215,6 +219,8 @@ double event_host_time(hb_server *s, hipEvent_t e)
 // recorded after the last piece is shared by the group's requests.
 int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
 {
+    const int ci = g.copy_stream;
+    hipStream_t cs = s->copy_in[ci];
     GroupPacker<Req> pk(rs, k);
     while (pk.done() < pk.total()) {
         const uint64_t want = std::min<uint64_t>(kPiece, pk.total() - pk.done());
@@ -230,9 +236,9 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
         }
         hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess)
-            e = s->copy_kernel ? launch_copy(s->d_arena + dst, g.dbuf + at, filled, s->copy_in)
-                               : hipMemcpyAsync(s->d_arena + dst, g.buf + at, filled, hipMemcpyHostToDevice, s->copy_in);
-        if (e == hipSuccess) e = hipEventRecord(ev, s->copy_in);
+            e = s->copy_kernel ? launch_copy(s->d_arena + dst, g.dbuf + at, filled, cs)
+                               : hipMemcpyAsync(s->d_arena + dst, g.buf + at, filled, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) e = hipEventRecord(ev, cs);
         if (e != hipSuccess) {
             if (ev) g.spare.push_back(ev);
             return hip_error(e, "hb_server: staging copy");
@@ -243,9 +249,10 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
     auto mark = std::make_shared<CopyMark>();
     hipError_t e = hipEventCreate(&mark->ev);
     if (e == hipSuccess) {
-        std::lock_guard<std::mutex> lk(s->copy_mu);
-        e = hipEventRecord(mark->ev, s->copy_in);
-        mark->seq = ++s->copy_seq;
+        std::lock_guard<std::mutex> lk(s->copy_mu[ci]);
+        e = hipEventRecord(mark->ev, cs);
+        mark->cs = ci;
+        mark->seq = ++s->copy_seq[ci];
     }
     if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
     for (int q = 0; q < k; ++q) rs[q]->copied = mark;
@@ -323,7 +330,7 @@ int launch_step(hb_server *s, int k, int c)
     uint64_t *hl = ho + kMaxStepN;
     uint8_t *hi = reinterpret_cast<uint8_t *>(hl + kMaxStepN);
     uint64_t m = 0;
-    const CopyMark *last = nullptr;
+    const CopyMark *last[kCopyStreams] = {};
     for (Req *r : st->reqs) {
         uint64_t pos = r->arena_off;
         for (uint64_t i = 0; i < r->n; ++i, ++m) {
@@ -332,12 +339,16 @@ int launch_step(hb_server *s, int k, int c)
             hi[m] = uint8_t(r->algo < 0 ? r->algos[i] : r->algo);
             pos += r->lens[i];
         }
-        if (r->copied && (!last || r->copied->seq > last->seq)) last = r->copied.get();
+        if (r->copied) {
+            const CopyMark *&l = last[r->copied->cs];
+            if (!l || r->copied->seq > l->seq) l = r->copied.get();
+        }
         r->st = St::Launched;
     }
-    // the copy stream is in order: once the step's latest mark is reached, every copy the
-    // step reads has landed
-    if (last) hipStreamWaitEvent(s->compute[k], last->ev, 0);
+    // each copy stream is in order: once the step's latest mark on each is reached, every
+    // copy the step reads has landed
+    for (const CopyMark *l : last)
+        if (l) hipStreamWaitEvent(s->compute[k], l->ev, 0);
     const double t_launch = s->now();
     for (Req *r : st->reqs) r->t_launch = t_launch;
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
@@ -527,8 +538,14 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
             (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->stager[w].dbuf), s->stager[w].buf, 0)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: device mapping of staging", e);
     }
-    if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
-        return fail(HB_EHIP, "hb_server_create: stream", e);
+    // copy streams: two when the process has eight hardware queues (two copy engines at
+    // work), else one; HB_SERVER_COPY_STREAMS overrides
+    if (const char *v = std::getenv("GPU_MAX_HW_QUEUES"); v && std::atoi(v) >= 8) s->n_copy = 2;
+    if (const char *v = std::getenv("HB_SERVER_COPY_STREAMS")) s->n_copy = std::max(1, std::min(kCopyStreams, std::atoi(v)));
+    for (int c = 0; c < s->n_copy; ++c)
+        if ((e = hipStreamCreateWithFlags(&s->copy_in[c], hipStreamNonBlocking)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: stream", e);
+    for (int w = 0; w < s->n_stagers; ++w) s->stager[w].copy_stream = w % s->n_copy;
     // Compute streams: one for short-chain steps, kLongStreamsDefault for long-chain ones,
     // two when the process has eight hardware queues (HB_SERVER_LONG_STREAMS overrides,
     // up to kStreams - 1).  Every stream may take one of
@@ -569,7 +586,7 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
             return fail(HB_ENOMEM, "hb_server_create: device step buffers", hipSuccess);
     }
     if ((e = hipEventCreate(&s->ref)) != hipSuccess) return fail(HB_EHIP, "hb_server_create: event", e);
-    if ((e = hipEventRecord(s->ref, s->copy_in)) != hipSuccess || (e = hipEventSynchronize(s->ref)) != hipSuccess)
+    if ((e = hipEventRecord(s->ref, s->copy_in[0])) != hipSuccess || (e = hipEventSynchronize(s->ref)) != hipSuccess)
         return fail(HB_EHIP, "hb_server_create: reference event", e);
     s->ref_host = s->now();
     hb_server *p = s.release();
@@ -756,9 +773,10 @@ void hb_server_destroy(hb_server *s)
         if (s->d_meta[k]) hipFree(s->d_meta[k]);
         if (s->compute[k]) hipStreamDestroy(s->compute[k]);
     }
-    if (s->copy_in) {
-        hipStreamSynchronize(s->copy_in);
-        hipStreamDestroy(s->copy_in);
+    for (hipStream_t c : s->copy_in) {
+        if (!c) continue;
+        hipStreamSynchronize(c);
+        hipStreamDestroy(c);
     }
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
     if (s->ref) hipEventDestroy(s->ref);
