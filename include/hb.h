@@ -267,7 +267,7 @@ typedef struct hb_server hb_server;
  * hbm_budget_bytes (request payload resident at once) and at most max_slots requests in
  * flight.  A background host thread admits queued requests in arrival order while both
  * limits hold; staging threads pack each admitted request's bytes into pinned memory and
- * copy them into the device on one copy stream; staged requests are batched into hashing
+ * copy them into the device on a copy stream; staged requests are batched into hashing
  * steps, requests holding a long chain apart from the rest, each kind on its own compute
  * stream, long-chain steps with the plan's long-chain path in one launch: three streams
  * in all (four with two long-chain streams), since streams beyond the process's hardware
