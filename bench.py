@@ -26,21 +26,27 @@ from pathlib import Path
 import numpy as np
 
 # Hardware queues per process for HIP (GPU_MAX_HW_QUEUES, read once when the runtime
-# starts): --hw-queues, default eight rather than HIP's four, so the serving loop can run
-# two long-chain streams beside its copy and short-chain streams and the process's own
-# default stream without two of them sharing a queue.  Set here, before anything
-# initialises the GPU; the value is reported in the output line.
-HW_QUEUES_DEFAULT = 8
+# starts).  The serving loop wants eight rather than HIP's four, so it can run two
+# long-chain streams and two copy streams beside its short-chain stream and the process's
+# own default stream without two of them sharing a queue; the batched mixed plan runs best
+# with the default four.  So the full run measures serving first, in a child process
+# started with --serve-hw-queues (default 8) before this process touches the GPU;
+# `--workload serve` alone uses 8, and --hw-queues sets the value for this process.  Set here, before anything initialises the GPU; the values used
+# are reported in the output line.
+SERVE_HW_QUEUES_DEFAULT = 8
 
 
 def _set_hw_queues(argv):
-    n = HW_QUEUES_DEFAULT
+    n = None
     for i, a in enumerate(argv):
         if a == "--hw-queues" and i + 1 < len(argv):
             n = int(argv[i + 1])
         elif a.startswith("--hw-queues="):
             n = int(a.split("=", 1)[1])
-    os.environ["GPU_MAX_HW_QUEUES"] = str(n)
+    if n is None and ("--workload=serve" in argv or ("serve" in argv and "--workload" in argv)):
+        n = SERVE_HW_QUEUES_DEFAULT
+    if n is not None:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(n)
 
 
 _set_hw_queues(sys.argv)
@@ -72,8 +78,11 @@ def parse():
                    help="skip the batched, mixed and serving sections of the default run")
     p.add_argument("--serve-seconds", type=float, default=15.0)
     p.add_argument("--no-overload", action="store_true", help="skip the serving overload burst")
-    p.add_argument("--hw-queues", type=int, default=HW_QUEUES_DEFAULT,
-                   help="HIP hardware queues for this process (GPU_MAX_HW_QUEUES, at most 32)")
+    p.add_argument("--hw-queues", type=int, default=None,
+                   help="HIP hardware queues for this process (GPU_MAX_HW_QUEUES, at most 32); "
+                        "default: the environment's (HIP's four), eight for --workload serve")
+    p.add_argument("--serve-hw-queues", type=int, default=SERVE_HW_QUEUES_DEFAULT,
+                   help="hardware queues of the child process that measures serving in the full run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     p.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -698,6 +707,25 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
     }
 
 
+def bench_serve_child(args):
+    """The serving section, measured in a child process with its own hardware-queue count
+    (--serve-hw-queues), started before this process initialises the GPU; this process
+    waits for it."""
+    import subprocess
+
+    cmd = [sys.executable, "-u", str(Path(__file__).resolve()), "--workload", "serve",
+           "--hw-queues", str(args.serve_hw_queues), "--serve-seconds", str(args.serve_seconds)]
+    if args.no_overload:
+        cmd.append("--no-overload")
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"serving child process failed with status {r.returncode}")
+    child = json.loads(r.stdout.strip().splitlines()[-1])
+    out = child["serving"]
+    out["hip_hw_queues"] = child["hip_hw_queues"]
+    return out
+
+
 def bench_serve_overload(pool, n_req=160_000, budget=64 << 30):
     """Overload burst: about 140 GB of requests (the serving distribution, the pool cycled)
     submitted at once against the 64 GiB device budget, with slots enough that the budget
@@ -741,6 +769,11 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "fixed":
+        # the serving child runs first, while this process has not touched the GPU yet
+        serving = None
+        if not args.only_headline:
+            print("bench: serving (child process)", file=sys.stderr, flush=True)
+            serving = bench_serve_child(args)
         rec = bench_fixed(args)
         rec["clock_note"] = _clock_ghz_note()
         if not args.only_headline:
@@ -754,8 +787,7 @@ def main():
             rec["paper_workload_digits9"] = bench_digits9(args)
             print("bench: incremental hashing", file=sys.stderr, flush=True)
             rec["incremental"] = bench_incremental(args)
-            print("bench: serving", file=sys.stderr, flush=True)
-            rec["serving"] = bench_serve(args, seconds=args.serve_seconds)
+            rec["serving"] = serving
     elif args.workload == "uneven":
         rec = {"batched_uneven": bench_uneven(args, steps=args.steps, warmup=args.warmup)}
     elif args.workload == "mixed":
@@ -768,7 +800,7 @@ def main():
         rec = {"paper_workload_digits9": bench_digits9(args)}
     else:
         rec = {"serving": bench_serve(args, seconds=args.serve_seconds)}
-    rec["hip_hw_queues"] = int(os.environ["GPU_MAX_HW_QUEUES"])
+    rec["hip_hw_queues"] = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     print(json.dumps(rec), flush=True)
 
 
