@@ -548,12 +548,13 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     for (int w = 0; w < s->n_stagers; ++w) s->stager[w].copy_stream = w % s->n_copy;
     // Compute streams: one for short-chain steps, kLongStreamsDefault for long-chain ones,
     // two when the process has eight hardware queues (HB_SERVER_LONG_STREAMS overrides,
-    // up to kStreams - 1).  Every stream may take one of
-    // the process's hardware queues (HIP's default is four, and the application's own
-    // default stream holds one once used); streams sharing a queue wait behind each
-    // other's kernels, and a copy stream sharing one with a compute stream stalls every
-    // request behind multi-millisecond chains.  So the loop keeps to three streams (copy,
-    // short, long) and its plans take no side stream.  Each stream keeps a plan per step
+    // up to kStreams - 1).  Every stream may take one of the process's hardware queues
+    // (HIP's default is four, and the application's own default stream holds one once
+    // used); streams sharing a queue wait behind each other's kernels, and a copy stream
+    // sharing one with a compute stream stalls every request behind multi-millisecond
+    // chains.  So with four queues the loop keeps to three streams (copy, short, long),
+    // with eight to five (two copy, two long), and its plans take no side stream.  Each
+    // stream keeps a plan per step
     // class, since an idle stream also runs the other class's steps: short-chain steps
     // are plain persistent-kernel plans (nothing in them reaches the long-chain
     // threshold); long-chain steps take the long-chain path in one launch with the bulk
