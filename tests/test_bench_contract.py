@@ -77,3 +77,21 @@ def test_record_traffic_scales_by_the_copy_kernel(tmp_path, monkeypatch):
     assert t["fixed:sha1"]["source_hash"] == bench.kernel_source_hash()
     monkeypatch.setattr(bench, "TRAFFIC_FILE", out)
     assert bench.measured_traffic("sm3", "fixed") == t["fixed:sm3"]["bytes_per_launch"]
+
+
+def test_hw_queue_setting(monkeypatch):
+    """The serving section runs with eight HIP hardware queues (`--workload serve`, or the
+    full run's child process); --hw-queues sets the count for the process; with neither
+    the environment's value is left alone."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", "4")
+    bench._set_hw_queues(["bench.py"])
+    assert bench.os.environ["GPU_MAX_HW_QUEUES"] == "4"
+    bench._set_hw_queues(["bench.py", "--workload", "serve"])
+    assert bench.os.environ["GPU_MAX_HW_QUEUES"] == str(bench.SERVE_HW_QUEUES_DEFAULT) == "8"
+    bench._set_hw_queues(["bench.py", "--workload=serve", "--hw-queues", "6"])
+    assert bench.os.environ["GPU_MAX_HW_QUEUES"] == "6"
+    bench._set_hw_queues(["bench.py", "--hw-queues=12"])
+    assert bench.os.environ["GPU_MAX_HW_QUEUES"] == "12"
