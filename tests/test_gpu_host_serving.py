@@ -273,9 +273,12 @@ def _long_chain_requests(seed=61):
                                  {"HB_SERVER_LONG_STREAMS": "2", "HB_SERVER_LONG_PLAN_FLAGS": "16"},
                                  {"HB_SERVER_LONG_PLAN_FLAGS": "16", "HB_LONG_MIN_BLOCKS": "2",
                                   "HB_LONG_SCRATCH_MB": "1"},
-                                 {"HB_SERVER_COPY": "kernel"}, {"HB_SERVER_COPY_STREAMS": "2"}],
+                                 {"HB_SERVER_COPY": "kernel"}, {"HB_SERVER_COPY_STREAMS": "2"},
+                                 {"HB_SERVER_STAGERS": "1"},
+                                 {"HB_SERVER_STAGERS": "8", "HB_SERVER_COPY_STREAMS": "2", "HB_SERVER_LONG_STREAMS": "2"}],
                          ids=["default_one_launch", "no_long_path", "long_path_side_stream", "two_long_streams",
-                              "direct_chains", "kernel_copies", "two_copy_streams"])
+                              "direct_chains", "kernel_copies", "two_copy_streams", "one_stager",
+                              "eight_stagers_two_copy_two_long"])
 def test_serving_long_chain_steps(hb, monkeypatch, env):
     """Requests holding long chains go to long-chain steps, whose plans by default run the
     longest chains rounds-only from precomputed schedule words (or, with a scratch too
