@@ -669,9 +669,14 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9
             tm = srv.trace(t)
             lat[k] = tm["done"] - sched[k]
             phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
+            # a step may be enqueued before its inputs' copy completes (the device then waits
+            # for the copy), so after stage_end the copy and the step launch run side by
+            # side: batch_wait counts only the time after the copy landed until the step was
+            # enqueued, exec_wait from the later of the two until the step began
+            ready = max(tm["launch"], tm["h2d_done"])
             parts[k] = (tm["admit"] - sched[k], tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
-                        tm["h2d_done"] - tm["stage_end"], tm["launch"] - max(tm["stage_end"], tm["h2d_done"]),
-                        tm["exec_begin"] - tm["launch"], tm["exec_end"] - tm["exec_begin"],
+                        tm["h2d_done"] - tm["stage_end"], ready - tm["h2d_done"],
+                        tm["exec_begin"] - ready, tm["exec_end"] - tm["exec_begin"],
                         tm["done"] - tm["exec_end"])
             done_max = max(done_max, tm["done"])
             srv.release(t)

@@ -299,7 +299,9 @@ int hb_server_submit(hb_server *server, int algo_or_mixed, const uint8_t *algos,
                      const uint8_t *messages, const uint64_t *offsets, const uint64_t *lengths,
                      uint64_t n, uint8_t *digests_out, uint64_t *ticket);
 
-/* Non-blocking completion check: *done = 1 when finished, with its status in *status. */
+/* Non-blocking completion check: *done = 1 when finished, with its status in *status.  For
+ * a finished request that failed, hb_last_error() on the calling thread then returns the
+ * failure's explanation, whichever server thread raised it. */
 int hb_server_poll(hb_server *server, uint64_t ticket, int *done, int *status);
 
 /* Cancel a request that has not been admitted yet: it leaves the queue and finishes with
@@ -313,7 +315,8 @@ int hb_server_cancel(hb_server *server, uint64_t ticket);
 int hb_server_release(hb_server *server, uint64_t ticket);
 
 /* Block until the request completes (or timeout_ms elapses, -1 = forever: HB_EBUSY on
- * timeout); *status receives its status. */
+ * timeout); *status receives its status.  If the request failed, hb_last_error() on the
+ * calling thread returns the failure's explanation, whichever server thread raised it. */
 int hb_server_wait(hb_server *server, uint64_t ticket, int64_t timeout_ms, int *status);
 
 /* Per-request timestamps in seconds on the server's steady clock: arrival (submit),
@@ -328,14 +331,17 @@ int hb_server_times(hb_server *server, uint64_t ticket, double *t_submit, double
  *   ADMIT        admitted (arena range and slot reserved)
  *   STAGE_BEGIN  a staging thread started packing it into pinned memory
  *   STAGE_END    its last host-to-device copy was enqueued
- *   H2D_DONE     that copy completed (device clock, mapped to the server clock)
- *   LAUNCH       the device step holding it was enqueued
+ *   H2D_DONE     that copy completed
+ *   LAUNCH       the device step holding it was enqueued (possibly before H2D_DONE: the
+ *                step then waits on the device for the copy)
  *   EXEC_BEGIN   that step's inputs and metadata were resident and hashing could start
- *                (device clock)
- *   EXEC_END     that step's digests were back in pinned host memory (device clock)
+ *   EXEC_END     that step's digests were back in pinned host memory
  *   DONE         its digests were in the caller's buffer and it was marked done
- * Times not reached yet are 0.  Returns HB_EINVAL for a null server, a negative nt, a null
- * t with nt > 0, or an unknown ticket. */
+ * H2D_DONE, EXEC_BEGIN and EXEC_END are the times the serving loop saw the device events
+ * complete (late by at most one pass of its polling loop), so every entry is on the same
+ * host clock and SUBMIT <= ADMIT <= STAGE_BEGIN <= STAGE_END <= H2D_DONE <= EXEC_BEGIN <=
+ * EXEC_END <= DONE, LAUNCH <= EXEC_BEGIN.  Times not reached yet are 0.  Returns HB_EINVAL
+ * for a null server, a negative nt, a null t with nt > 0, or an unknown ticket. */
 enum {
     HB_TRACE_SUBMIT = 0,
     HB_TRACE_ADMIT = 1,

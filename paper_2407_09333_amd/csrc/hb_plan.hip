@@ -19,6 +19,7 @@
 #include "hb_device.hpp"
 #include "hb_internal.hpp"
 #include "hb_long.hpp"
+#include "hb_plan_rules.hpp"
 
 namespace hb {
 
@@ -26,7 +27,6 @@ namespace hb {
 // Layout constants
 // ---------------------------------------------------------------------------------------
 
-constexpr uint32_t kBins = 16448;      // block-count keys per algorithm: key = min(nb, kBins - 1)
 constexpr uint32_t kLdsKeys = 1024;    // keys below this are counted in LDS first
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr int kThreads = 256;          // 4 waves per workgroup
@@ -69,6 +69,7 @@ struct PlanMeta {
                               // follow the long_n scheduled ones in the segment)
     uint32_t direct_first[4]; // first direct-lane index of each algorithm (padded to 64 lanes)
     uint32_t bulk_waves;      // persistent-kernel waves that take items (the others exit)
+    unsigned long long max_chain;  // longest chain in the batch: block count x ops per block
 };
 
 // Device workspace (pointers fixed for the plan's life).
@@ -92,12 +93,7 @@ struct PlanWs {
 // scratch cannot hold all of them: slot 0 = SM3, 1 = SHA-1, 2 = MD5.
 __host__ __device__ constexpr int long_order(int o) { return o == 0 ? SM3 : (o == 1 ? SHA1 : MD5); }
 
-__device__ __forceinline__ uint32_t msg_key(uint64_t len, int sort)
-{
-    if (!sort) return 0;
-    const uint64_t nb = (len + 8u) / 64u + 1u;
-    return nb >= kBins ? kBins - 1 : uint32_t(nb);
-}
+__device__ __forceinline__ uint32_t msg_key(uint64_t len, int sort) { return sort ? sort_key(len) : 0u; }
 
 __device__ __forceinline__ int msg_algo(const PlanDesc &d, uint64_t i)
 {
@@ -134,6 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_zero(PlanWs ws)
         m->bulk_waves = 0xffffffffu;
         m->long_blocks = 0;
         m->max_key = 0;
+        m->max_chain = 0;
         m->queue = 0;
         m->total_cost = 0;
     }
@@ -145,10 +142,12 @@ __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
 {
     __shared__ uint32_t lh[3 * kLdsKeys];
     __shared__ uint32_t lmax;
+    __shared__ unsigned long long lchain;
     const PlanDesc d = *ws.desc;
     for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) lh[i] = 0;
-    if (threadIdx.x == 0) lmax = 0;
+    if (threadIdx.x == 0) { lmax = 0; lchain = 0; }
     uint32_t my_max = 0;
+    unsigned long long my_chain = 0;
     __syncthreads();
     const uint64_t step = uint64_t(gridDim.x) * kThreads;
     for (uint64_t base = uint64_t(blockIdx.x) * kThreads; base < d.n; base += step) {
@@ -156,8 +155,11 @@ __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
         if (i < d.n) {
             const int a = msg_algo(d, i);
             if (a >= 0 && a < 3) {
-                const uint32_t key = msg_key(d.lens[i], d.sort);
+                const uint64_t len = d.lens[i];
+                const uint32_t key = msg_key(len, d.sort);
                 my_max = key > my_max ? key : my_max;
+                const unsigned long long chain = block_count(len) * algo_cost(a);
+                my_chain = chain > my_chain ? chain : my_chain;
                 const uint32_t slot = uint32_t(a) * kBins + key;
                 const uint32_t first = __builtin_amdgcn_readfirstlane(slot);
                 const uint64_t same = __ballot(slot == first);
@@ -174,12 +176,14 @@ __global__ __launch_bounds__(kThreads) void k_hist(PlanWs ws)
         }
     }
     if (my_max) atomicMax(&lmax, my_max);
+    if (my_chain) atomicMax(&lchain, my_chain);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < 3 * kLdsKeys; i += kThreads) {
         const uint32_t c = lh[i];
         if (c) atomicAdd(&ws.hist[(i / kLdsKeys) * kBins + (i % kLdsKeys)], c);
     }
     if (threadIdx.x == 0 && lmax) atomicMax(&ws.meta->max_key, lmax);
+    if (threadIdx.x == 0 && lchain) atomicMax(&ws.meta->max_chain, lchain);
 }
 
 // Exclusive scan, longest key first within each algorithm; segments padded to whole
@@ -367,12 +371,16 @@ __global__ __launch_bounds__(kThreads) void k_zero_invalid(PlanWs ws)
 // Choose the long-chain messages: within each algorithm's segment, the leading messages
 // (longest first) whose key reaches long_min_key, taken a wave (64 messages) at a time
 // while the waves' scratch regions fit; a wave's region is as many wave-blocks as its
-// first (longest) message has blocks.  The candidates that do not fit become direct
-// chains (below).  One workgroup; each long-chain wave is algorithm-uniform.
+// longest message has blocks (wave_region_blocks: lane 0's count below the saturated key,
+// the largest over the wave's lanes once keys saturate and the order among them is
+// arbitrary).  The candidates that do not fit become direct chains (below).  One
+// workgroup; each long-chain wave is algorithm-uniform.
 __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
 {
     __shared__ uint32_t part[kScanThreads];
-    __shared__ uint32_t s_run, s_wave, s_stop, s_cand[3];
+    __shared__ unsigned long long part64[kScanThreads];
+    __shared__ unsigned long long s_run;
+    __shared__ uint32_t s_wave, s_stop, s_cand[3];
     const PlanDesc d = *ws.desc;
     PlanMeta *m = ws.meta;
     if (threadIdx.x == 0) { s_run = 0; s_wave = 0; }
@@ -402,26 +410,28 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
         for (uint32_t c0 = 0; c0 < nw; c0 += kScanThreads) {
             if (s_stop) break;
             const uint32_t wi = c0 + threadIdx.x;
-            uint32_t cost = 0;
+            unsigned long long cost = 0;
             if (wi < nw) {
-                const uint32_t idx = ws.sorted[m->seg_pos[a] + wi * 64u];
-                cost = uint32_t((d.lens[idx] + 8u) / 64u + 1u);
+                const uint32_t *lane_idx = ws.sorted + m->seg_pos[a] + wi * 64u;
+                // clamped to capacity + 1, which never fits, so the sums stay small
+                cost = wave_region_blocks([&](uint32_t l) { return d.lens[lane_idx[l]]; },
+                                          min(64u, cand - wi * 64u), uint64_t(ws.sched_blocks) + 1u);
             }
-            part[threadIdx.x] = cost;
+            part64[threadIdx.x] = cost;
             __syncthreads();
             for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
-                const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+                const unsigned long long v = threadIdx.x >= off ? part64[threadIdx.x - off] : 0ull;
                 __syncthreads();
-                part[threadIdx.x] += v;
+                part64[threadIdx.x] += v;
                 __syncthreads();
             }
-            const uint64_t base = uint64_t(s_run) + part[threadIdx.x] - cost;
+            const unsigned long long base = s_run + part64[threadIdx.x] - cost;
             const bool fits = wi < nw && base + cost <= ws.sched_blocks && w0 + wi < ws.max_long_waves;
             if (fits) ws.wave_base[w0 + wi] = uint32_t(base);
             const uint32_t nfit = uint32_t(__syncthreads_count(fits));
             __syncthreads();
             if (threadIdx.x == 0) {
-                if (nfit) s_run += part[nfit - 1];
+                if (nfit) s_run += part64[nfit - 1];
                 if (nfit < kScanThreads) s_stop = 1;
             }
             taken += nfit;
@@ -436,9 +446,9 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        ws.wave_base[s_wave] = s_run;  // end of the last region
+        ws.wave_base[s_wave] = uint32_t(s_run);  // end of the last region
         m->long_first[3] = s_wave * 64u;
-        m->long_blocks = s_run;
+        m->long_blocks = uint32_t(s_run);
         // The candidates the scratch could not hold run as direct chains, each on a lane
         // of its own at the highest priority.  At most max_direct_waves waves: if more are
         // needed, only the messages whose chain cost (blocks x ops per block) reaches the
@@ -481,12 +491,8 @@ __global__ __launch_bounds__(kScanThreads) void k_long_scan(PlanWs ws)
         // enough that its items (total_cost, in the same op units as a chain) would finish in
         // 1/bulk_margin of the longest chain's time at one op per wave issue slot.  Fewer
         // bulk waves leave the long chains more issue slots and memory bandwidth.
-        uint64_t crit = 0;
-        for (int a = 0; a < 3; ++a) {
-            if (s_cand[a] == 0) continue;
-            const uint32_t idx = ws.sorted[m->seg_pos[a]];
-            crit = max(crit, uint64_t(msg_key(d.lens[idx], d.sort)) * algo_cost(a));
-        }
+        const bool any_cand = s_cand[0] + s_cand[1] + s_cand[2] > 0;
+        const uint64_t crit = any_cand ? m->max_chain : 0;
         if (crit && d.bulk_margin) {
             const uint64_t w = (uint64_t(d.bulk_margin) * m->total_cost + crit - 1) / crit;
             m->bulk_waves = uint32_t(min<uint64_t>(max<uint64_t>(w, kMinBulkWaves), 0xffffffffull));
@@ -531,7 +537,7 @@ __global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
         if (i >= m.long_n[a]) continue;  // a padding lane
         const uint32_t idx = ws.sorted[m.seg_pos[a] + i];
         const uint64_t len = d.lens[idx];
-        const uint64_t nb = (len + 8u) / 64u + 1u, blk = gb - ws.wave_base[lo];
+        const uint64_t nb = block_count(len), blk = gb - ws.wave_base[lo];
         if (blk >= nb) continue;  // shorter than the wave's longest message
         uint32_t *wr = ws.sched + uint64_t(ws.wave_base[lo]) * kWaveBlockWords;
         uint32_t w[16], out[kSchedWords];
@@ -556,6 +562,18 @@ __global__ __launch_bounds__(kThreads) void k_sched(PlanWs ws)
 // max_long_waves run the direct chains (ordinary compression) of the long messages the
 // scratch could not hold, so no long chain shares the persistent kernel's issue slots at
 // ordinary priority.
+// One message's chain by the ordinary compression, the next block prefetched (SHA-1, SM3).
+__device__ __forceinline__ void direct_chain(const PlanDesc &d, int a, uint32_t idx)
+{
+    const uint8_t *msg = d.msgs + d.offs[idx];
+    const uint64_t len = d.lens[idx];
+    uint32_t st[8];
+    uint8_t *out = d.out + uint64_t(idx) * d.stride;
+    if (a == MD5) { hash_message<MD5>(msg, len, st); store_digest<MD5>(out, st, d.stride); }
+    else if (a == SHA1) { hash_message_prefetch<SHA1>(msg, len, st); store_digest<SHA1>(out, st, d.stride); }
+    else { hash_message_prefetch<SM3>(msg, len, st); store_digest<SM3>(out, st, d.stride); }
+}
+
 template <int SCHED>
 __device__ __forceinline__ void long_lane(const PlanWs &ws, uint32_t g)
 {
@@ -575,14 +593,7 @@ __device__ __forceinline__ void long_lane(const PlanWs &ws, uint32_t g)
         const uint32_t i = dg - m.direct_first[a];
         if (i >= m.direct_n[a]) return;  // padding lane
         __builtin_amdgcn_s_setprio(3);
-        const uint32_t idx = ws.sorted[m.seg_pos[a] + m.long_n[a] + i];
-        const uint8_t *msg = d.msgs + d.offs[idx];
-        const uint64_t len = d.lens[idx];
-        uint32_t st[8];
-        uint8_t *out = d.out + uint64_t(idx) * d.stride;
-        if (a == MD5) { hash_message<MD5>(msg, len, st); store_digest<MD5>(out, st, d.stride); }
-        else if (a == SHA1) { hash_message_prefetch<SHA1>(msg, len, st); store_digest<SHA1>(out, st, d.stride); }
-        else { hash_message_prefetch<SM3>(msg, len, st); store_digest<SM3>(out, st, d.stride); }
+        direct_chain(d, a, ws.sorted[m.seg_pos[a] + m.long_n[a] + i]);
         __builtin_amdgcn_s_setprio(0);
         return;
     }
@@ -593,21 +604,24 @@ __device__ __forceinline__ void long_lane(const PlanWs &ws, uint32_t g)
     if (i >= m.long_n[a]) return;  // padding lane
     __builtin_amdgcn_s_setprio(3);
     const uint32_t idx = ws.sorted[m.seg_pos[a] + i];
-    const uint64_t nb = (d.lens[idx] + 8u) / 64u + 1u;
-    uint32_t st[8];
-    uint8_t *out = d.out + uint64_t(idx) * d.stride;
+    const uint64_t nb = block_count(d.lens[idx]);
     if constexpr (SCHED) {
-        const uint32_t *wr = ws.sched + uint64_t(ws.wave_base[g / 64u]) * kWaveBlockWords;
-        const uint32_t l = g % 64u;
-        if (a == MD5) { chain_from_sched<MD5>(wr, l, nb, st); store_digest<MD5>(out, st, d.stride); }
-        else if (a == SHA1) { chain_from_sched<SHA1>(wr, l, nb, st); store_digest<SHA1>(out, st, d.stride); }
-        else { chain_from_sched<SM3>(wr, l, nb, st); store_digest<SM3>(out, st, d.stride); }
+        const uint32_t w = g / 64u;
+        // k_long_scan sizes a region for its wave's longest message, so nb never exceeds
+        // it; the check keeps any lane from reading past its region all the same
+        if (nb <= uint64_t(ws.wave_base[w + 1]) - ws.wave_base[w]) {
+            uint32_t st[8];
+            uint8_t *out = d.out + uint64_t(idx) * d.stride;
+            const uint32_t *wr = ws.sched + uint64_t(ws.wave_base[w]) * kWaveBlockWords;
+            const uint32_t l = g % 64u;
+            if (a == MD5) { chain_from_sched<MD5>(wr, l, nb, st); store_digest<MD5>(out, st, d.stride); }
+            else if (a == SHA1) { chain_from_sched<SHA1>(wr, l, nb, st); store_digest<SHA1>(out, st, d.stride); }
+            else { chain_from_sched<SM3>(wr, l, nb, st); store_digest<SM3>(out, st, d.stride); }
+        } else {
+            direct_chain(d, a, idx);
+        }
     } else {
-        const uint8_t *msg = d.msgs + d.offs[idx];
-        const uint64_t len = d.lens[idx];
-        if (a == MD5) { hash_message<MD5>(msg, len, st); store_digest<MD5>(out, st, d.stride); }
-        else if (a == SHA1) { hash_message_prefetch<SHA1>(msg, len, st); store_digest<SHA1>(out, st, d.stride); }
-        else { hash_message_prefetch<SM3>(msg, len, st); store_digest<SM3>(out, st, d.stride); }
+        direct_chain(d, a, idx);
     }
     __builtin_amdgcn_s_setprio(0);
 }
@@ -867,20 +881,27 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         else
             hipLaunchKernelGGL((k_hash_fused<0, 0>), grid, dim3(kThreads), 0, s, ws, long_blocks);
     } else if (p->long_on) {
-        // fork: the long chains start first on the side stream and run beside the bulk
-        hipEventRecord(p->ev_fork, s);
-        hipStreamWaitEvent(p->side, p->ev_fork, 0);
+        // fork: the long chains start first on the side stream and run beside the bulk.  A
+        // failed fork or join is returned: unjoined, the run's stream could report the
+        // digests done before the long chains wrote theirs.
+        hipError_t fe = hipEventRecord(p->ev_fork, s);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+        if (fe != hipSuccess) return fe;
         const int long_blocks =
             int((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
         if (p->long_sched) hipLaunchKernelGGL(k_hash_long<1>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
         else hipLaunchKernelGGL(k_hash_long<0>, dim3(long_blocks), dim3(kThreads), 0, p->side, ws);
-        hipEventRecord(p->ev_join, p->side);
+        if ((fe = hipGetLastError()) != hipSuccess) return fe;
+        if ((fe = hipEventRecord(p->ev_join, p->side)) != hipSuccess) return fe;
     }
     if (!fused) {
         if (p->variant == 1) hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
         else hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
     }
-    if (p->long_on && !fused) hipStreamWaitEvent(s, p->ev_join, 0);  // join
+    if (p->long_on && !fused) {  // join
+        const hipError_t je = hipStreamWaitEvent(s, p->ev_join, 0);
+        if (je != hipSuccess) return je;
+    }
     if (ev.first) {
         hipEventRecord(ev.second, s);
         p->ev_pending.push_back(ev);

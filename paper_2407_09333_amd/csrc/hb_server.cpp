@@ -33,6 +33,7 @@
 #include "../../include/hb.h"
 #include "hb_arena.hpp"
 #include "hb_internal.hpp"
+#include "hb_outcome.hpp"
 #include "hb_policy.hpp"
 #include "hb_stage.hpp"
 
@@ -64,7 +65,7 @@ struct CopyMark {
     hipEvent_t ev = nullptr;
     int cs = 0;         // copy stream it was recorded on
     uint64_t seq = 0;   // position among the marks on that copy stream
-    double t = -1;      // host time of ev, once read
+    double t = -1;      // host time the serving loop first saw ev complete
     CopyMark() = default;
     CopyMark(const CopyMark &) = delete;
     CopyMark &operator=(const CopyMark &) = delete;
@@ -85,12 +86,13 @@ struct Req {
     uint64_t payload = 0;           // sum of lengths
     uint64_t arena_off = Arena::kFail;
     St st = St::Pending;
-    int status = HB_OK;
+    Outcome res;                    // status, and the text of a failure
     double t_submit = 0, t_admit = 0, t_h2d = 0, t_done = 0;
     double t_stage_begin = 0;       // host time a staging thread took it
     double t_staged = 0;            // host time its copies were enqueued
     double t_launch = 0;            // host time its step was launched
-    double t_exec0 = 0, t_exec1 = 0;  // its step's hashing began / digests copied (device clock)
+    double t_exec0 = 0, t_exec1 = 0;  // its step's inputs resident / digests back (host time the
+                                      // loop saw the step's events complete)
     std::shared_ptr<CopyMark> copied;  // its staging group's copies
     bool stalled = false;           // was held back at the head of the queue
     int cls = 0;                    // 0: short chains only, 1: has a long chain
@@ -103,6 +105,7 @@ struct Step {
     int algo = 0;
     hipEvent_t begin = nullptr;     // recorded when the step's inputs are resident
     hipEvent_t done = nullptr;
+    double t_begin = -1;            // host time the loop first saw `begin` complete
 };
 
 // A staging thread's pinned ring.  Each copy occupies a segment of the ring until the copy
@@ -173,6 +176,9 @@ struct hb_server {
     bool copy_kernel = false;       // payload copies by kernel from the rings' device mapping
     std::mutex copy_mu[kCopyStreams];  // orders the copy marks' records on each copy stream
     uint64_t copy_seq[kCopyStreams] = {};  // (under copy_mu)
+    // marks not yet seen complete, per copy stream in record order (under copy_mu): the
+    // loop polls their heads and stamps each with the host time it first saw it done
+    std::deque<std::shared_ptr<CopyMark>> unseen[kCopyStreams];
     hipStream_t compute[kStreams] = {};
     hb_plan *plan[kStreams][2] = {}; // per stream, by the class of the step it runs
     uint8_t *h_meta[kStreams] = {}; // pinned, coherent: offsets | lengths | ids | digests
@@ -180,8 +186,6 @@ struct hb_server {
     uint8_t *d_meta[kStreams] = {};
     std::unique_ptr<Step> busy[kStreams];
     int n_streams = kStreams;       // compute streams in use
-    hipEvent_t ref = nullptr;
-    double ref_host = 0;
     std::chrono::steady_clock::time_point t0;
     // stats
     std::atomic<uint64_t> completed{0}, steps{0}, stalls{0}, peak{0};
@@ -203,14 +207,29 @@ hipEvent_t take_event(hb_server *s)
         return e;
     }
     hipEvent_t e = nullptr;
-    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
 }
 
-double event_host_time(hb_server *s, hipEvent_t e)
+// The text of the last error on this thread (set by set_error / hip_error).
+std::string last_error_text() { return std::string(hb_last_error()); }
+
+// Trace times are host times at which the loop saw a device event complete.  Every time
+// on a request's trace is then on one clock (the server's steady clock), so the phases
+// between them are never negative; each device time is late by at most one pass of the
+// loop.  (Device timestamps mapped through one reference event drift against the host
+// clock over a long run and carry the reference's own synchronisation latency.)
+void poll_marks(hb_server *s)
 {
-    float ms = 0.f;
-    if (e && hipEventElapsedTime(&ms, s->ref, e) == hipSuccess) return s->ref_host + double(ms) * 1e-3;
-    return s->now();
+    for (int c = 0; c < s->n_copy; ++c) {
+        std::lock_guard<std::mutex> lk(s->copy_mu[c]);
+        auto &q = s->unseen[c];
+        while (!q.empty()) {
+            const hipError_t e = hipEventQuery(q.front()->ev);
+            if (e == hipErrorNotReady) break;  // later marks on this in-order stream are not done either
+            q.front()->t = s->now();
+            q.pop_front();
+        }
+    }
 }
 
 // Pack the group rs[0..k) (arena ranges following each other, see GroupPacker) into
@@ -247,12 +266,15 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
         g.head = at + filled;
     }
     auto mark = std::make_shared<CopyMark>();
-    hipError_t e = hipEventCreate(&mark->ev);
+    hipError_t e = hipEventCreateWithFlags(&mark->ev, hipEventDisableTiming);
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(s->copy_mu[ci]);
         e = hipEventRecord(mark->ev, cs);
-        mark->cs = ci;
-        mark->seq = ++s->copy_seq[ci];
+        if (e == hipSuccess) {
+            mark->cs = ci;
+            mark->seq = ++s->copy_seq[ci];
+            s->unseen[ci].push_back(mark);
+        }
     }
     if (e != hipSuccess) return hip_error(e, "hb_server: copy event");
     for (int q = 0; q < k; ++q) rs[q]->copied = mark;
@@ -291,11 +313,12 @@ void stager_loop(hb_server *s, int w)
         const double t0 = s->now();
         for (Req *r : grp) r->t_stage_begin = t0;
         const int rc = stage_group(s, g, grp.data(), int(grp.size()));
+        const std::string why = rc != HB_OK ? last_error_text() : std::string();
         {
             std::lock_guard<std::mutex> lk(s->mu);
             const double t1 = s->now();
             for (Req *r : grp) {
-                if (rc != HB_OK) r->status = rc;
+                if (rc != HB_OK) r->res.fail(rc, why);
                 r->t_staged = t1;
                 s->staged[r->cls].push_back(r);
             }
@@ -346,9 +369,11 @@ int launch_step(hb_server *s, int k, int c)
         r->st = St::Launched;
     }
     // each copy stream is in order: once the step's latest mark on each is reached, every
-    // copy the step reads has landed
+    // copy the step reads has landed.  A failed wait fails the step: hashing arena bytes
+    // whose copy has not landed would give wrong digests without an error.
+    hipError_t we = hipSuccess;
     for (const CopyMark *l : last)
-        if (l) hipStreamWaitEvent(s->compute[k], l->ev, 0);
+        if (l && we == hipSuccess) we = hipStreamWaitEvent(s->compute[k], l->ev, 0);
     const double t_launch = s->now();
     for (Req *r : st->reqs) r->t_launch = t_launch;
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
@@ -361,6 +386,7 @@ int launch_step(hb_server *s, int k, int c)
         s->busy[k] = std::move(st);
         return rc;
     };
+    if (we != hipSuccess) return fail(hip_error(we, "hb_server: step wait on its input copies"));
     // Metadata in and digests out are copied by kernels on the compute stream through the
     // pinned buffer's device mapping, not by the copy engine: a copy-engine transfer queued
     // behind a running step would hold up the payload copies of later requests.
@@ -387,31 +413,33 @@ int launch_step(hb_server *s, int k, int c)
 }
 
 // Finish the step on stream k: digests to the callers' buffers, release memory and slots.
-void finish_step(hb_server *s, int k, int status)
+// A failed step (status != HB_OK) fails each of its requests with `why`.
+void finish_step(hb_server *s, int k, int status, const std::string &why)
 {
     Step *st = s->busy[k].get();
     const uint64_t stride = st->mixed ? 32 : uint64_t(digest_size(st->algo));
     const uint8_t *hd = s->h_meta[k] + kMaxStepN * 17;
+    poll_marks(s);  // every mark the step waited on is complete if the step is
     const double t = s->now();
-    const double t_exec0 = st->begin && status == HB_OK ? event_host_time(s, st->begin) : t;
-    const double t_exec1 = st->done && status == HB_OK ? event_host_time(s, st->done) : t;
+    const double t_exec0 = st->t_begin >= 0 ? st->t_begin : t;
     uint64_t m = 0;
     for (Req *r : st->reqs) {
         r->t_exec0 = t_exec0;
-        r->t_exec1 = t_exec1;
+        r->t_exec1 = t;
         const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
-        if (r->status == HB_OK) r->status = status;
-        if (r->status == HB_OK) {
+        r->res.fail(status, why);
+        if (r->res.status == HB_OK) {
             if (ds == stride) std::memcpy(r->out, hd + m * stride, r->n * stride);
             else
                 for (uint64_t i = 0; i < r->n; ++i) std::memcpy(r->out + i * ds, hd + (m + i) * stride, ds);
         }
         m += r->n;
         if (r->copied) {
-            CopyMark &c = *r->copied;
-            if (r->status == HB_OK && c.t < 0) c.t = event_host_time(s, c.ev);
-            r->t_h2d = r->status == HB_OK ? c.t : t;
+            const CopyMark &c = *r->copied;
+            r->t_h2d = c.t >= 0 ? std::min(c.t, t_exec0) : t_exec0;
             r->copied.reset();
+        } else {
+            r->t_h2d = r->t_staged;  // nothing to copy
         }
         if (r->payload) s->arena.release(r->arena_off, r->payload);
     }
@@ -481,20 +509,32 @@ void loop(hb_server *s)
             if (launch_cls[k] < 0) continue;
             int rc = launch_step(s, k, launch_cls[k]);
             if (rc != HB_OK) {
+                std::string why = last_error_text();
                 s->fatal = rc;
                 if (s->busy[k]) {
-                    if (hipStreamSynchronize(s->compute[k]) != hipSuccess) rc = HB_EHIP;
-                    finish_step(s, k, rc);
+                    const hipError_t e = hipStreamSynchronize(s->compute[k]);
+                    if (e != hipSuccess) {
+                        rc = HB_EHIP;
+                        why += std::string("; stream: ") + hipGetErrorString(e);
+                    }
+                    finish_step(s, k, rc, why);
                 }
             }
         }
-        // 3. completions
+        // 3. completions: input copies seen done, steps begun, steps done (in this order, so
+        // a request's trace times never run backwards)
+        poll_marks(s);
         bool progressed = false;
         for (int k = 0; k < s->n_streams; ++k) {
-            if (!s->busy[k]) continue;
-            hipError_t q = hipEventQuery(s->busy[k]->done);
-            if (q == hipSuccess) { finish_step(s, k, HB_OK); progressed = true; }
-            else if (q != hipErrorNotReady) { finish_step(s, k, HB_EHIP); progressed = true; }
+            Step *st = s->busy[k].get();
+            if (!st) continue;
+            if (st->t_begin < 0 && st->begin && hipEventQuery(st->begin) == hipSuccess) st->t_begin = s->now();
+            const hipError_t q = hipEventQuery(st->done);
+            if (q == hipSuccess) { finish_step(s, k, HB_OK, std::string()); progressed = true; }
+            else if (q != hipErrorNotReady) {
+                finish_step(s, k, HB_EHIP, std::string("hb_server: step failed on the device: ") + hipGetErrorString(q));
+                progressed = true;
+            }
         }
         if (!progressed && !admitted) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
@@ -586,10 +626,6 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
         if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_meta[k]), meta_bytes(kMaxStepN))) != hipSuccess)
             return fail(HB_ENOMEM, "hb_server_create: device step buffers", hipSuccess);
     }
-    if ((e = hipEventCreate(&s->ref)) != hipSuccess) return fail(HB_EHIP, "hb_server_create: event", e);
-    if ((e = hipEventRecord(s->ref, s->copy_in[0])) != hipSuccess || (e = hipEventSynchronize(s->ref)) != hipSuccess)
-        return fail(HB_EHIP, "hb_server_create: reference event", e);
-    s->ref_host = s->now();
     hb_server *p = s.release();
     for (int w = 0; w < p->n_stagers; ++w) p->stager[w].thr = std::thread(stager_loop, p, w);
     p->thr = std::thread(loop, p);
@@ -650,7 +686,9 @@ int hb_server_poll(hb_server *s, uint64_t ticket, int *done, int *status)
     auto it = s->all.find(ticket);
     if (it == s->all.end()) return set_error(HB_EINVAL, "hb_server_poll: unknown ticket");
     *done = it->second->st == St::Done;
-    if (status) *status = it->second->status;
+    if (status) *status = it->second->res.status;
+    // a failed request's explanation becomes this thread's last error
+    if (*done) it->second->res.deliver([](int st, const std::string &why) { set_error(st, why); });
     return HB_OK;
 }
 
@@ -666,7 +704,7 @@ int hb_server_cancel(hb_server *s, uint64_t ticket)
         auto q = std::find(s->pending.begin(), s->pending.end(), r);
         if (q == s->pending.end()) return set_error(HB_EBUSY, "hb_server_cancel: request already admitted");
         s->pending.erase(q);
-        r->status = HB_ECANCELED;
+        r->res.fail(HB_ECANCELED, "hb_server_cancel: cancelled before admission");
         r->t_admit = r->t_h2d = r->t_done = s->now();
         r->st = St::Done;
     }
@@ -697,7 +735,9 @@ int hb_server_wait(hb_server *s, uint64_t ticket, int64_t timeout_ms, int *statu
     if (timeout_ms < 0) s->cv_done.wait(g, ready);
     else if (!s->cv_done.wait_for(g, std::chrono::milliseconds(timeout_ms), ready))
         return set_error(HB_EBUSY, "hb_server_wait: timed out");
-    if (status) *status = r->status;
+    if (status) *status = r->res.status;
+    // a failed request's explanation becomes this thread's last error
+    r->res.deliver([](int st, const std::string &why) { set_error(st, why); });
     return HB_OK;
 }
 
@@ -779,8 +819,8 @@ void hb_server_destroy(hb_server *s)
         hipStreamSynchronize(c);
         hipStreamDestroy(c);
     }
+    for (auto &q : s->unseen) q.clear();
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
-    if (s->ref) hipEventDestroy(s->ref);
     if (s->d_arena) hipFree(s->d_arena);
     delete s;
 }

@@ -133,10 +133,10 @@ def test_alone_equals_in_the_mix(hb):
 
 
 @pytest.mark.slow
-def test_full_size_sm3_uneven_sampled(hb):
+def test_full_size_sm3_uneven_all(hb):
     """SM3 over 2^22 messages with lengths uniform on 0..4096 (about 8 GiB), bucketed plan
-    as timed by the benchmark; 20,000 sampled digests plus the longest and shortest
-    messages checked against the oracle one by one."""
+    as timed by the benchmark; every digest checked against the oracle (the whole buffer
+    copied back and hashed on all host cores)."""
     import torch
 
     b = workloads.cfg_sm3_uneven(device="cuda")
@@ -144,17 +144,14 @@ def test_full_size_sm3_uneven_sampled(hb):
     plan = hb.Plan(b.n, flags=hb.PLAN_GRAPH)
     got = plan.run(b.messages, b.offsets, b.lengths, algo=2)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(3)
-    idx = np.unique(np.concatenate([rng.choice(b.n, 20_000, replace=False), [0, b.n - 1],
-                                    np.argsort(b.lengths)[:50], np.argsort(b.lengths)[-50:]]))
-    _check_sampled(hb, b, idx, got, 2)
+    _check_all(b, got, 2)
     plan.close()
 
 
 @pytest.mark.slow
-def test_full_size_mixed_8gib_sampled(hb):
+def test_full_size_mixed_8gib_all(hb):
     """Mixed 8 GiB batch (log-normal lengths, median 512 B, cap 1 MiB), one fused
-    persistent launch; sampled digests including the 100 longest messages."""
+    persistent launch as timed by the benchmark; every digest checked against the oracle."""
     import torch
 
     b = workloads.cfg_mixed_8gib(device="cuda")
@@ -162,23 +159,16 @@ def test_full_size_mixed_8gib_sampled(hb):
     plan = hb.Plan(b.n, flags=hb.PLAN_GRAPH)
     got = plan.run(b.messages, b.offsets, b.lengths, algos=b.algos)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(4)
-    idx = np.unique(np.concatenate([rng.choice(b.n, 20_000, replace=False), np.argsort(b.lengths)[-100:]]))
-    _check_sampled(hb, b, idx, got, b.algos)
+    _check_all(b, got, b.algos)
     plan.close()
 
 
-def _check_sampled(hb, b, idx, got, algo):
-    import torch
-
-    lens = b.lengths[idx]
-    offs = b.offsets[idx]
-    parts = [b.messages[int(o):int(o + L)].cpu().numpy() for o, L in zip(offs, lens)]
-    host = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
-    noffs = workloads.packed(lens)
-    a = algo[idx] if isinstance(algo, np.ndarray) else algo
-    want = oracle.hash_batch(a, host, noffs, lens, out_stride=got.shape[1])
-    assert_same(got[torch.from_numpy(idx).cuda()].cpu().numpy(), want, "sampled full size")
+def _check_all(b, got, algo):
+    host = b.messages.cpu().numpy()
+    print(f"  oracle over {b.n} messages, {host.size / 1e9:.2f} GB", flush=True)
+    want = oracle.hash_batch(algo, host, b.offsets, b.lengths, out_stride=got.shape[1])
+    del host
+    assert_same(got.cpu().numpy(), want, "full size, every digest")
 
 
 def test_long_chain_direct_cap(hb, monkeypatch):
@@ -236,3 +226,59 @@ def test_long_chain_path(hb, monkeypatch, scratch_mb, min_blocks):
     plan = hb.Plan(n, flags=hb.PLAN_NO_LONG)
     assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, "no long path")
     plan.close()
+
+
+def _saturated_long_batch(seed=77):
+    """70 SM3, 5 SHA-1 and 5 MD5 messages, every length distinct and between 1.1 and
+    3 MiB -- past the ~1.05 MB point where block-count sort keys saturate -- with the
+    shorter ones of each algorithm at lower indices, plus a few short messages."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for algo, count in ((2, 70), (1, 5), (0, 5)):
+        base = np.linspace(1.1 * 2**20, 3 * 2**20, count).astype(np.uint64)
+        jitter = rng.permutation(count).astype(np.uint64) * np.uint64(7) + np.uint64(algo)
+        parts.append((np.sort(base + jitter), np.full(count, algo, np.uint8)))
+    short = rng.integers(0, 5000, size=200).astype(np.uint64)
+    lens = np.concatenate([p[0] for p in parts] + [short])
+    algos = np.concatenate([p[1] for p in parts] + [rng.integers(0, 3, size=200).astype(np.uint8)])
+    assert np.unique(lens[:80]).size == 80
+    offs = workloads.packed(lens)
+    msgs = workloads.host_random_bytes(int(lens.sum()), seed)
+    return msgs, offs, lens, algos
+
+
+@pytest.mark.parametrize("scratch_mb", ["1024", "2048", "4096"])
+def test_long_chains_past_key_saturation(hb, monkeypatch, scratch_mb):
+    """Many same-algorithm messages above the saturated sort key in one plan: their order
+    inside that key is arbitrary, so a long-chain wave's scratch region must hold its
+    longest lane.  1 GiB holds no such wave (all run as direct chains); 2 GiB holds the
+    first SM3 wave and 4 GiB both SM3 waves (rounds-only from precomputed words), the rest
+    running as direct chains.  Every digest against the oracle, with the long chains beside
+    the bulk on a side stream and in one launch."""
+    monkeypatch.setenv("HB_LONG_SCRATCH_MB", scratch_mb)
+    msgs, offs, lens, algos = _saturated_long_batch()
+    print(f"case saturated long chains scratch={scratch_mb} n={lens.size}", flush=True)
+    want = oracle.hash_batch(algos, msgs, offs, lens)
+    for flags in (hb.PLAN_GRAPH, hb.PLAN_LONG_INLINE):
+        plan = hb.Plan(lens.size, flags=flags)
+        buf, out = guarded_out(lens.size, 32)
+        plan.run(msgs, offs, lens, algos=algos, out=out)
+        check_guard(buf, lens.size, 32)
+        assert_same(out.cpu().numpy(), want, f"saturated long flags={flags} scratch={scratch_mb}")
+        plan.close()
+    # one algorithm per plan run too (the segment holds only saturated keys)
+    sm3 = np.nonzero(algos == 2)[0]
+    plan = hb.Plan(sm3.size, flags=hb.PLAN_GRAPH)
+    got = plan.run(msgs, offs[sm3], lens[sm3], algo=2).cpu().numpy()
+    assert_same(got, want[sm3, :32], f"saturated long sm3 only scratch={scratch_mb}")
+    plan.close()
+
+
+def test_long_chains_past_key_saturation_host(hb):
+    """The same batch through hash_batch_host (pageable host memory, one chunk, the
+    host pipeline's long-chain plan), every digest against the oracle."""
+    msgs, offs, lens, algos = _saturated_long_batch(seed=78)
+    print(f"case saturated long chains host n={lens.size}", flush=True)
+    want = oracle.hash_batch(algos, msgs, offs, lens)
+    got = hb.hash_batch_host(msgs, offs, lens, algos=algos, chunk_bytes=1 << 30)
+    assert_same(got, want, "saturated long host")

@@ -60,3 +60,68 @@ def test_serving_policy(tmp_path, sanitize):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "policy ok" in out.stdout
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_plan_long_chain_regions(tmp_path, sanitize):
+    """Host model of the batched plan's long-chain scratch assignment, using the plan's own
+    sizing rules (hb_plan_rules.hpp): with block-count keys saturated above about 1.05 MB,
+    a wave's region must come from its longest lane, not its first.  The model shows the
+    first-lane rule reading past its region on a 1.5 MiB message ordered ahead of a 3 MiB
+    one, and that the rule in use never does over random bucketed orders."""
+    exe = tmp_path / "plan_region_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", str(HERE / "cpp" / "plan_region_check.cpp"), "-o", str(exe)]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "plan region ok" in out.stdout
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_request_failure_text_reaches_the_caller(tmp_path, sanitize):
+    """A serving request failed on a staging thread or the loop carries its explanation to
+    the thread that waits for it (hb_outcome.hpp, used by hb_server_wait / hb_server_poll):
+    the waiter's per-thread error text is the failure's, other threads' are untouched, and
+    the first failure wins."""
+    exe = tmp_path / "outcome_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", str(HERE / "cpp" / "outcome_check.cpp"), "-o", str(exe)]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "outcome ok" in out.stdout
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_host_hashing_code_under_sanitizers(tmp_path, sanitize):
+    """The CPU oracle (oracle/hash_oracle.c) and the library's host share of a CPU + GPU
+    split (csrc/hb_cpu.cpp) built with the address and undefined-behaviour sanitizers:
+    every length 0..300 and 1 MiB-class messages, each in an exact-size heap buffer, all
+    three algorithms, with the two codes agreeing on every digest."""
+    root = HERE.parent
+    flags = ["-O1", "-g"] + (["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                              "-fno-sanitize-recover=undefined"] if sanitize else [])
+    obj = tmp_path / "hash_oracle.o"
+    r = subprocess.run(["gcc", "-std=c11", *flags, "-c", str(root / "oracle" / "hash_oracle.c"), "-o", str(obj)],
+                       capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    exe = tmp_path / "hash_sanitize_check"
+    cmd = ["g++", "-std=c++17", *flags, "-pthread", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           str(HERE / "cpp" / "hash_sanitize_check.cpp"), str(root / "paper_2407_09333_amd" / "csrc" / "hb_cpu.cpp"),
+           str(obj), "-o", str(exe), "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "sanitized hashing ok" in out.stdout
