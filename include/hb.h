@@ -202,6 +202,25 @@ double hb_plan_kernel_ms(hb_plan *plan);
 
 void hb_plan_destroy(hb_plan *plan);
 
+/*
+ * hash_batch_bucketed_noalloc -- for callers that cannot allocate (code under hipGraph
+ * capture, serving loops and harnesses that forbid hipMalloc): the batched form of
+ * hb_plan_run without a plan.  Same arguments, digests and steps as hb_plan_run with
+ * HB_PLAN_LONG_INLINE (bucketing, longest-first persistent launch, long chains beside the
+ * bulk in one launch), except that every long chain is a direct chain (no schedule
+ * scratch) and nothing is captured in a graph.  The workspace is a static device array of
+ * about 4.6 MiB that each GPU the library runs on holds until the process ends; the first
+ * call on a device looks up its address there.  No call allocates or frees memory.
+ *   n            at most 2^20 messages: larger n returns HB_EINVAL before anything is
+ *                enqueued
+ * Every call on a GPU uses that GPU's one array (each run clears what it needs first), so
+ * calls that overlap on one GPU -- on different streams or from different threads --
+ * race and give wrong digests: serialise them, for example on one stream.
+ */
+int hash_batch_bucketed_noalloc(const uint8_t *algos, int algo, const uint8_t *messages,
+                                const uint64_t *offsets, const uint64_t *lengths, uint64_t n,
+                                uint8_t *digests_out, void *stream);
+
 /* ------------------------------------------------------------------------------------ */
 /* Host-resident inputs: chunked H2D copies overlapped with hashing.                      */
 /* ------------------------------------------------------------------------------------ */

@@ -1005,6 +1005,89 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
     return HB_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Allocation-free batched run: the plan's pipeline on a workspace that lives in a static
+// device array, for callers that cannot allocate (code under graph capture, serving loops
+// that must not call the allocator).  Long chains run as direct chains beside the bulk in
+// one launch (no schedule scratch), at most kStaticMaxN messages per call.
+// ---------------------------------------------------------------------------------------
+
+constexpr uint64_t kStaticMaxN = 1ull << 20;
+constexpr uint64_t kStaticLongWaves = 3;  // no scheduled long waves: wave_base holds only the end
+constexpr uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr uint64_t kStaticDesc = up256(sizeof(PlanDesc)), kStaticMeta = up256(sizeof(PlanMeta));
+constexpr uint64_t kStaticBins = up256(3ull * kBins * 4);
+constexpr uint64_t kStaticSorted = up256((kStaticMaxN + 3ull * 64 * kMaxMpl) * 4);
+constexpr uint64_t kStaticOrder = up256((kStaticMaxN / 64 + 4) * 4);
+constexpr uint64_t kStaticWaveBase = up256((kStaticLongWaves + 1) * 4);
+constexpr uint64_t kStaticBytes =
+    kStaticDesc + kStaticMeta + 3 * kStaticBins + kStaticSorted + kStaticOrder + kStaticWaveBase;
+
+// The workspace: one copy per device, held until the process ends.  Host code never uses
+// this name as an address (on the host it is only a handle); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+constexpr int kStaticDevices = 64;
+
+struct StaticDevice {
+    std::once_flag once;
+    int status = HB_OK;
+    std::string why;
+    uint8_t *ptr = nullptr;  // device address of `scratch` on this device
+    int cus = 0;
+};
+
+static StaticDevice g_static[kStaticDevices];
+
+// Set-up on the first call on a device, with that device current: the array's address
+// and the CU count (hipGetSymbolAddress and an attribute query; nothing is allocated).
+static StaticDevice *static_device(int dev)
+{
+    if (dev < 0 || dev >= kStaticDevices) return nullptr;
+    StaticDevice *sd = &g_static[dev];
+    std::call_once(sd->once, [sd, dev] {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            sd->status = HB_EHIP;
+            sd->why = std::string("hash_batch_bucketed_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return;
+        }
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess || cus <= 0) {
+            sd->status = HB_EHIP;
+            sd->why = std::string("hash_batch_bucketed_noalloc: CU count: ") + hipGetErrorString(e);
+            return;
+        }
+        sd->ptr = static_cast<uint8_t *>(ptr);
+        sd->cus = cus;
+    });
+    return sd;
+}
+
+// The plan workspace carved out of the device's copy of the array.
+static PlanWs static_ws(uint8_t *base, int cus)
+{
+    PlanWs ws{};
+    uint8_t *c = base;
+    ws.desc = reinterpret_cast<PlanDesc *>(c); c += kStaticDesc;
+    ws.meta = reinterpret_cast<PlanMeta *>(c); c += kStaticMeta;
+    ws.hist = reinterpret_cast<uint32_t *>(c); c += kStaticBins;
+    ws.cursor = reinterpret_cast<uint32_t *>(c); c += kStaticBins;
+    ws.bin_start = reinterpret_cast<uint32_t *>(c); c += kStaticBins;
+    ws.sorted = reinterpret_cast<uint32_t *>(c); c += kStaticSorted;
+    ws.order = reinterpret_cast<uint32_t *>(c); c += kStaticOrder;
+    ws.wave_base = reinterpret_cast<uint32_t *>(c);
+    ws.sched = nullptr;  // no schedule scratch: every long chain is a direct chain
+    ws.sched_blocks = 0;
+    ws.max_long_waves = uint32_t(kStaticLongWaves);
+    ws.max_direct_waves = uint32_t(cus) * 4u;
+    ws.max_n = kStaticMaxN;
+    return ws;
+}
+
 }  // namespace hb
 
 using namespace hb;
@@ -1169,6 +1252,54 @@ void hb_plan_destroy(hb_plan *p)
     if (p->ev_join) hipEventDestroy(p->ev_join);
     if (p->alloc) hipFree(p->alloc);
     delete p;
+}
+
+int hash_batch_bucketed_noalloc(const uint8_t *algos, int algo, const uint8_t *messages, const uint64_t *offsets,
+                                const uint64_t *lengths, uint64_t n, uint8_t *digests_out, void *stream)
+{
+    if (!algos && digest_size(algo) == 0) return set_error(HB_EINVAL, "hash_batch_bucketed_noalloc: unknown algorithm id");
+    if (n == 0) return HB_OK;
+    if (n > kStaticMaxN)
+        return set_error(HB_EINVAL, "hash_batch_bucketed_noalloc: n exceeds the static workspace's 2^20 messages");
+    if (!messages || !offsets || !lengths || !digests_out)
+        return set_error(HB_EINVAL, "hash_batch_bucketed_noalloc: null device pointer");
+    if (reinterpret_cast<uintptr_t>(digests_out) & 3u)
+        return set_error(HB_EINVAL, "hash_batch_bucketed_noalloc: digests_out must be 4-byte aligned");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hash_batch_bucketed_noalloc: hipGetDevice");
+    StaticDevice *sd = static_device(dev);
+    if (!sd) return set_error(HB_EINVAL, "hash_batch_bucketed_noalloc: device index out of range");
+    if (sd->status != HB_OK) return set_error(sd->status, sd->why);
+    // a plan object on the stack: launch settings only, its workspace is the static array
+    hb_plan p;
+    p.ws = static_ws(sd->ptr, sd->cus);
+    p.flags = HB_PLAN_LONG_INLINE;
+    p.device = dev;
+    p.cus = sd->cus;
+    p.long_on = true;
+    p.long_sched = false;
+    p.long_min_key = 256;
+    p.side = nullptr;  // long chains and bulk in one launch
+    PlanDesc d{};
+    d.algos = algos;
+    d.msgs = messages;
+    d.offs = offsets;
+    d.lens = lengths;
+    d.out = digests_out;
+    d.n = n;
+    d.stride = algos ? 32u : uint32_t(digest_size(algo));
+    d.algo = algos ? 0 : algo;
+    d.sort = 1;
+    d.mpl = p.mpl;
+    d.long_min_key = p.long_min_key;
+    d.bulk_margin = p.bulk_margin;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, d, p.ws.desc);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = enqueue_pipeline(&p, s, false);
+    if (e != hipSuccess) return hip_error(e, "hash_batch_bucketed_noalloc: launch");
+    return HB_OK;
 }
 
 }  // extern "C"

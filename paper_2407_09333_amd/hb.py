@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
             L.hb_plan_kernel_ms.restype = ctypes.c_double
             L.hb_plan_destroy.argtypes = [_vp]
             L.hb_plan_destroy.restype = None
+        if hasattr(L, "hash_batch_bucketed_noalloc"):
+            L.hash_batch_bucketed_noalloc.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _vp]
         if hasattr(L, "hash_batch_host"):
             L.hash_batch_host.argtypes = [_vp, _i, _vp, _vp, _vp, _u64, _vp, _u64]
         if hasattr(L, "hash_batch_host_split"):
@@ -288,6 +290,25 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_MAX_N = 1 << 20  # the static workspace's message limit (include/hb.h)
+
+
+def hash_batch_bucketed_noalloc(messages, offsets, lengths, algo=None, algos=None, out=None, stream=None):
+    """Batched form without a plan or any allocation in the library
+    (hash_batch_bucketed_noalloc); digests as Plan.run."""
+    torch = _torch()
+    msgs, offs, lens = _dev_u8(messages), _dev_i64(offsets), _dev_i64(lengths)
+    n = offs.numel()
+    al = _dev_u8(algos) if algos is not None else None
+    a = algo_id(algo) if algo is not None else 0
+    stride = 32 if al is not None else DIGEST_SIZE.get(a, 32)
+    if out is None:
+        out = torch.empty((n, stride), dtype=torch.uint8, device=msgs.device)
+    check(lib().hash_batch_bucketed_noalloc(_ptr(al), a, _ptr(msgs), _ptr(offs), _ptr(lens), n, _ptr(out),
+                                            _stream_ptr(stream)))
+    return out
 
 
 def hash_batch_host(messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
