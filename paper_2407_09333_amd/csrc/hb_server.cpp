@@ -309,9 +309,9 @@ void stager_loop(hb_server *s, int w)
                 s->to_stage.pop_front();
             }
             s->staging_inflight += int(grp.size());
+            const double t0 = s->now();
+            for (Req *r : grp) r->t_stage_begin = t0;
         }
-        const double t0 = s->now();
-        for (Req *r : grp) r->t_stage_begin = t0;
         const int rc = stage_group(s, g, grp.data(), int(grp.size()));
         const std::string why = rc != HB_OK ? last_error_text() : std::string();
         {
@@ -343,6 +343,7 @@ int launch_step(hb_server *s, int k, int c)
         if (take == 0) return HB_OK;
         st->reqs.assign(q.begin(), q.begin() + take);
         q.erase(q.begin(), q.begin() + take);
+        for (Req *r : st->reqs) r->st = St::Launched;
     }
     st->n = n;
     st->algo = st->reqs[0]->algo;
@@ -366,7 +367,6 @@ int launch_step(hb_server *s, int k, int c)
             const CopyMark *&l = last[r->copied->cs];
             if (!l || r->copied->seq > l->seq) l = r->copied.get();
         }
-        r->st = St::Launched;
     }
     // each copy stream is in order: once the step's latest mark on each is reached, every
     // copy the step reads has landed.  A failed wait fails the step: hashing arena bytes
@@ -374,8 +374,12 @@ int launch_step(hb_server *s, int k, int c)
     hipError_t we = hipSuccess;
     for (const CopyMark *l : last)
         if (l && we == hipSuccess) we = hipStreamWaitEvent(s->compute[k], l->ev, 0);
-    const double t_launch = s->now();
-    for (Req *r : st->reqs) r->t_launch = t_launch;
+    {
+        // trace times are read under the lock (hb_server_trace), so they are written under it
+        std::lock_guard<std::mutex> g(s->mu);
+        const double t_launch = s->now();
+        for (Req *r : st->reqs) r->t_launch = t_launch;
+    }
     uint64_t *dof = reinterpret_cast<uint64_t *>(s->d_meta[k]);
     uint64_t *dl = dof + kMaxStepN;
     uint8_t *di = reinterpret_cast<uint8_t *>(dl + kMaxStepN);
@@ -422,13 +426,14 @@ void finish_step(hb_server *s, int k, int status, const std::string &why)
     poll_marks(s);  // every mark the step waited on is complete if the step is
     const double t = s->now();
     const double t_exec0 = st->t_begin >= 0 ? st->t_begin : t;
+    // digests first; a request's status, trace times and state change together under the
+    // lock, where hb_server_wait / poll / trace read them
+    std::vector<double> t_h2d(st->reqs.size());
     uint64_t m = 0;
-    for (Req *r : st->reqs) {
-        r->t_exec0 = t_exec0;
-        r->t_exec1 = t;
+    for (size_t q = 0; q < st->reqs.size(); ++q) {
+        Req *r = st->reqs[q];
         const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
-        r->res.fail(status, why);
-        if (r->res.status == HB_OK) {
+        if (status == HB_OK && r->res.status == HB_OK) {  // res is only written under the lock
             if (ds == stride) std::memcpy(r->out, hd + m * stride, r->n * stride);
             else
                 for (uint64_t i = 0; i < r->n; ++i) std::memcpy(r->out + i * ds, hd + (m + i) * stride, ds);
@@ -436,10 +441,10 @@ void finish_step(hb_server *s, int k, int status, const std::string &why)
         m += r->n;
         if (r->copied) {
             const CopyMark &c = *r->copied;
-            r->t_h2d = c.t >= 0 ? std::min(c.t, t_exec0) : t_exec0;
+            t_h2d[q] = c.t >= 0 ? std::min(c.t, t_exec0) : t_exec0;
             r->copied.reset();
         } else {
-            r->t_h2d = r->t_staged;  // nothing to copy
+            t_h2d[q] = -1;  // nothing to copy: the time its staging ended
         }
         if (r->payload) s->arena.release(r->arena_off, r->payload);
     }
@@ -447,7 +452,12 @@ void finish_step(hb_server *s, int k, int status, const std::string &why)
     if (st->done) s->ev_pool.push_back(st->done);
     {
         std::lock_guard<std::mutex> g(s->mu);
-        for (Req *r : st->reqs) {
+        for (size_t q = 0; q < st->reqs.size(); ++q) {
+            Req *r = st->reqs[q];
+            r->res.fail(status, why);
+            r->t_exec0 = t_exec0;
+            r->t_exec1 = t;
+            r->t_h2d = t_h2d[q] >= 0 ? t_h2d[q] : r->t_staged;
             r->t_done = t;
             r->st = St::Done;
             s->slots_used--;

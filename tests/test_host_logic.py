@@ -125,3 +125,52 @@ def test_host_hashing_code_under_sanitizers(tmp_path, sanitize):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "sanitized hashing ok" in out.stdout
+
+
+CLANG = Path("/opt/rocm/llvm/bin/clang++")
+
+
+@pytest.fixture(scope="module")
+def server_check_exe(tmp_path_factory):
+    """The serving-loop check built once per sanitizer (see the test below)."""
+    if not CLANG.exists():
+        pytest.skip("clang++ with sanitizer runtimes not found")
+    built = {}
+
+    def get(sanitize):
+        if sanitize not in built:
+            exe = tmp_path_factory.mktemp("server_check") / "server_check"
+            cpp = HERE / "cpp"
+            cmd = [str(CLANG), "-std=c++17", "-O1", "-g", f"-fsanitize={sanitize}", "-fno-omit-frame-pointer",
+                   "-I", str(cpp / "fakehip"), "-I", str(HERE.parent / "include"), str(cpp / "server_check.cpp"),
+                   str(cpp / "fakehip" / "fake_hip.cpp"),
+                   str(HERE.parent / "paper_2407_09333_amd" / "csrc" / "hb_server.cpp"), "-o", str(exe), "-lpthread"]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            assert r.returncode == 0, r.stderr
+            built[sanitize] = exe
+        return built[sanitize]
+
+    return get
+
+
+@pytest.mark.parametrize("env", [{}, {"GPU_MAX_HW_QUEUES": "8"}, {"HB_SERVER_COPY": "kernel"},
+                                 {"HB_SERVER_STAGERS": "1"}], ids=["default", "8queues", "kernelcopy", "1stager"])
+@pytest.mark.parametrize("sanitize", ["thread", "address,undefined"], ids=["tsan", "asan"])
+def test_serving_loop_on_host_stand_in(server_check_exe, sanitize, env):
+    """The serving loop itself (csrc/hb_server.cpp, compiled unchanged) on the CPU against a
+    host-only stand-in for the HIP runtime (tests/cpp/fakehip: in-order streams on host
+    threads, events, stream waits, copies) and for the plan's hashing (a per-message
+    fingerprint), under ThreadSanitizer and under AddressSanitizer + UBSan: three client
+    threads submit, cancel and wait on 180 requests against a 2 MiB budget; every request's
+    slots hold its own messages' fingerprints, and no event is destroyed or recorded again
+    while in flight, no stream waits on an event never recorded, no destroyed stream or
+    event is used, and every event created is destroyed.  Clang's sanitizers are used:
+    GCC 11's ThreadSanitizer does not follow condition-variable waits on the steady clock."""
+    import os
+
+    exe = server_check_exe(sanitize)
+    run_env = dict(os.environ, **env, TSAN_OPTIONS="halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    out = subprocess.run([str(exe), "60"], capture_output=True, text=True, timeout=300, env=run_env)
+    assert out.returncode == 0, out.stdout + out.stderr[-4000:]
+    assert "server ok" in out.stdout
+    assert "WARNING: ThreadSanitizer" not in out.stderr, out.stderr[-4000:]
