@@ -57,8 +57,10 @@ sys.path.insert(0, str(ROOT))
 ALGO_NAMES = ["md5", "sha1", "sm3"]
 # VALU instructions per 64-byte block on gfx950 (one lane): the compression with every
 # three-input boolean function as one v_bitop3_b32, rotates as v_alignbit_b32 and sums as
-# v_add3_u32 / v_xad_u32, plus one v_perm_b32 per message word for realignment / byte order.
-OPS_PER_BLOCK = {"md5": 340, "sha1": 613, "sm3": 1348}
+# v_add3_u32 / v_xad_u32, plus, for SHA-1 and SM3, one v_perm_b32 per message word for the
+# byte order.  MD5's words are little-endian as loaded, so on dword-aligned messages (the
+# fixed-length batches) it needs none: 64 steps x 5 + 4.
+OPS_PER_BLOCK = {"md5": 324, "sha1": 613, "sm3": 1348}
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
 ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12     # 39.32 T int32 lane-ops/s
 HBM_PEAK_GBS = 8000.0
@@ -78,6 +80,8 @@ def parse():
                    help="skip the batched, mixed and serving sections of the default run")
     p.add_argument("--serve-seconds", type=float, default=15.0)
     p.add_argument("--no-overload", action="store_true", help="skip the serving overload burst")
+    p.add_argument("--save-inputs", default=None, metavar="DIR",
+                   help="also write the seeded length / algorithm arrays of each section as .npy files")
     p.add_argument("--hw-queues", type=int, default=None,
                    help="HIP hardware queues for this process (GPU_MAX_HW_QUEUES, at most 32); "
                         "default: the environment's (HIP's four), eight for --workload serve")
@@ -243,6 +247,40 @@ def bench_fixed(args):
             "alu_frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
             "hbm_frac_payload": round(payload / t / 1e9 / HBM_PEAK_GBS, 4),
         }
+    # MD5 again with its message words staged through LDS (HB_PLAIN_LDS=1, coalesced loads,
+    # the same digests): the variant kept as an option, reported beside the default
+    os.environ["HB_PLAIN_LDS"] = "1"
+    try:
+        lds_ms = []
+        for k in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hb.hash_batch_fixed(0, msgs, n, L, out=outs[0], stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            if k >= args.warmup:
+                lds_ms.append(e0.elapsed_time(e1))
+    finally:
+        del os.environ["HB_PLAIN_LDS"]
+    per_algo["md5"]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
+    per_algo["md5"]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
+    # what a plain read of the same 1 GiB reaches on this GPU (torch's sum kernel, read-only
+    # streaming): the practical HBM ceiling MD5 is compared with
+    words = msgs.view(torch.int32)
+    rd_ms = []
+    for k in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        words.sum(dtype=torch.int64)
+        e1.record(stream)
+        e1.synchronize()
+        if k >= args.warmup:
+            rd_ms.append(e0.elapsed_time(e1))
+    hbm_read = {"kernel": "torch sum over the same 1 GiB (read-only stream)",
+                "ms": round(float(np.mean(rd_ms)), 4), "ms_min": round(float(np.min(rd_ms)), 4),
+                "TBps": round(payload / (float(np.mean(rd_ms)) / 1e3) / 1e12, 3),
+                "TBps_best": round(payload / (float(np.min(rd_ms)) / 1e3) / 1e12, 3)}
+    per_algo["md5"]["frac_of_measured_read_stream"] = round(float(np.mean(rd_ms)) / kms["md5"], 4)
     dom = max(kms, key=kms.get)
     t_dom = kms[dom] / 1e3
     ops_dom = blocks * OPS_PER_BLOCK[dom]
@@ -263,6 +301,7 @@ def bench_fixed(args):
                                "uniform random bytes); one step = the three plain launches",
                    "messages": n, "msg_len": L, "payload_bytes_per_step": 3 * payload},
         "per_algo": per_algo,
+        "hbm_read_stream": hbm_read,
         "roofline": roofline,
         "device": info,
         "kernel_source": kernel_source_hash(),
@@ -329,6 +368,22 @@ def _time_ms(fn, steps, warmup, stream):
     return _time_stats(fn, steps, warmup, stream)["mean"]
 
 
+def _inputs_record(args, name, **arrays):
+    """Provenance of a section's seeded inputs: numpy's version and each length / algorithm
+    array's SHA-256 (the bytes are regenerated from the seeds in workloads.py); with
+    --save-inputs DIR the arrays are also written there as .npy files."""
+    rec = {"numpy": np.__version__, "generator": "paper_2407_09333_amd.workloads",
+           "sha256": {k: hashlib.sha256(np.ascontiguousarray(v).tobytes()).hexdigest() for k, v in arrays.items()}}
+    out_dir = getattr(args, "save_inputs", None)
+    if out_dir:
+        d = Path(out_dir)
+        d.mkdir(parents=True, exist_ok=True)
+        for k, v in arrays.items():
+            np.save(d / f"{name}_{k}.npy", np.ascontiguousarray(v), allow_pickle=False)
+        rec["saved_to"] = str(d)
+    return rec
+
+
 def bench_uneven(args, steps=5, warmup=2):
     """SM3 over 2^22 messages with lengths uniform on 0..4096 bytes, packed: the bucketed
     persistent plan (hipGraph) against the plain one-lane-per-message kernel."""
@@ -345,9 +400,15 @@ def bench_uneven(args, steps=5, warmup=2):
     t_plan = st_plan["mean"]
     plan_e = hb.Plan(b.n, flags=0)
     cfg = plan.config()
-    plan_e.set_config(cfg["waves_per_cu"], cfg["msgs_per_lane"])
+    plan_e.set_config(cfg["waves_per_cu"], cfg["msgs_per_lane"], cfg["variant"])
     _time_ms(lambda: plan_e.run(b.messages, offs, lens, algo=2, out=out), steps, 1, stream)
     k_ms = plan_e.kernel_ms()
+    # the same plan at the untuned defaults (16 waves per CU, one message per lane, default
+    # bursts), to state what the autotuner's choice gains
+    plan_d = hb.Plan(b.n, flags=hb.PLAN_GRAPH)
+    t_default = _time_ms(lambda: plan_d.run(b.messages, offs, lens, algo=2, out=out), steps, 1, stream)
+    default_cfg = plan_d.config()
+    plan_d.close()
     t_plain = _time_ms(lambda: hb.hash_batch(2, b.messages, offs, lens, out=out), steps, warmup, stream)
     payload = int(b.lengths.sum())
     blocks = int(((b.lengths.astype(np.int64) + 8) // 64 + 1).sum())
@@ -364,6 +425,12 @@ def bench_uneven(args, steps=5, warmup=2):
         "alu_frac_plain": round(ops / (t_plain / 1e3) / 1e12 / ALU_PEAK_TOPS, 4),
         "critical_path_ms_bound": round(_critical_path_ms(b.lengths, None, 2), 3),
         "plan_config": cfg,
+        "plan_config_note": "autotuned: waves per CU x messages per lane x load scheme (variant 0 default "
+                            "bursts, 1 next-block prefetch, 2 one block per load, 3 two-block and 4 "
+                            "four-block bursts), timed on this batch",
+        "untuned_config": default_cfg, "untuned_ms": round(t_default, 3),
+        "autotune_gain": round(t_default / t_plan, 3),
+        "inputs": _inputs_record(args, "sm3_uneven", lengths=b.lengths),
     }
     plan.close()
     plan_e.close()
@@ -408,6 +475,7 @@ def bench_mixed(args, steps=3, warmup=1):
         "critical_path_note": "longest chain x ops per block x 4 cycles at 2.1 GHz; the bound uses the "
                               "rounds-only chain (schedule words precomputed off the chain), the other "
                               "figure the full compression",
+        "inputs": _inputs_record(args, "mixed_8gib", lengths=b.lengths, algos=b.algos),
     }
     plan.close()
     del b, offs, lens, al, out
@@ -614,101 +682,152 @@ SERVE_PARTS = ("admit_wait", "stager_wait", "pack", "copy", "batch_wait", "exec_
 SERVE_FIXED_RATE = 8000.0  # req/s (about 7 GB/s of payload): the headline offered load
 
 
-def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.2, 0.5, 0.7, 0.9), cap_burst=8192):
+def _serve_open_loop(srv, pool, rate, n_req, seed=105):
+    """n_req requests (the pool cycled) at Poisson arrivals of the given rate; latency is
+    completion time - scheduled arrival time (no coordinated omission).  Returns the stats
+    of the run and each request's trace split into phases."""
+    pool_size = len(pool)
+    arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n_req))
+    tickets, sched = [None] * n_req, np.zeros(n_req)
+    s0 = srv.stats()
+    start = srv.now() + 0.05
+    payload = 0
+    for k in range(n_req):
+        r = pool[k % pool_size]
+        target = start + arrivals[k]
+        while True:
+            d = target - srv.now()
+            if d <= 0:
+                break
+            if d > 0.002:
+                time.sleep(d - 0.001)
+        sched[k] = target
+        tickets[k] = srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)
+        payload += int(r.lengths.sum())
+    lat = np.zeros(n_req)
+    phases = np.zeros((n_req, 3))
+    parts = np.zeros((n_req, len(SERVE_PARTS)))
+    done_max = 0.0
+    for k, t in enumerate(tickets):
+        srv.wait(t)
+        tm = srv.trace(t)
+        lat[k] = tm["done"] - sched[k]
+        phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
+        # a step may be enqueued before its inputs' copy completes (the device then waits
+        # for the copy), so after stage_end the copy and the step launch run side by side:
+        # batch_wait counts only the time after the copy landed until the step was
+        # enqueued, exec_wait from the later of the two until the step began
+        ready = max(tm["launch"], tm["h2d_done"])
+        parts[k] = (tm["admit"] - sched[k], tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
+                    tm["h2d_done"] - tm["stage_end"], ready - tm["h2d_done"],
+                    tm["exec_begin"] - ready, tm["exec_end"] - tm["exec_begin"],
+                    tm["done"] - tm["exec_end"])
+        done_max = max(done_max, tm["done"])
+        srv.release(t)
+    s1 = srv.stats()
+    span = done_max - start
+    return {"offered_req_per_s": round(rate, 1), "requests": n_req,
+            "achieved_req_per_s": round(n_req / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "p999_ms": round(float(np.percentile(lat, 99.9)) * 1e3, 3),
+            "achieved_GBps": round(payload / span / 1e9, 3),
+            "steps": s1["steps"] - s0["steps"], "admission_stalls": s1["stalls"] - s0["stalls"],
+            "median_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.median(phases, 0)],
+            "p99_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.percentile(phases, 99, axis=0)],
+            "parts_ms": {name: [round(float(np.percentile(parts[:, j], q)) * 1e3, 3) for q in (50, 99)]
+                         for j, name in enumerate(SERVE_PARTS)}}
+
+
+SERVE_TRACK_FRAC = 0.97   # an offered rate is sustained if the achieved rate is at least this share of it
+SERVE_P99_BOUND_MS = 10.0  # ... and p99 stays below this
+
+
+def _sustained(run):
+    return (run["achieved_req_per_s"] >= SERVE_TRACK_FRAC * run["offered_req_per_s"]
+            and run["p99_ms"] <= SERVE_P99_BOUND_MS)
+
+
+def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), cap_burst=8192, trial_s=1.5):
     """Open-loop Poisson arrivals; each request 1..10,000 messages (log-uniform count),
     algorithm uniform over the three, lengths log-normal (median 256 B, cap 64 KiB); device
-    budget 64 GiB.  Capacity C is measured first with a saturating burst of 8,192 requests;
-    then requests arrive at the fixed headline rate of 8,000 req/s, and at 0.2, 0.5, 0.7 and
-    0.9 C; latency = completion time - scheduled arrival time (no coordinated omission)."""
+    budget 64 GiB.  A saturating burst of 8,192 requests gives a first estimate C_burst
+    (adjacent requests then share transfers, so it overstates what Poisson arrivals get);
+    the capacity C is then the highest offered rate, found by bisection over short
+    open-loop trials between 0.25 and 1.1 C_burst, at which the achieved rate tracks the
+    offered one (>= 97 %) with p99 <= 10 ms.  The headline is p50 / p99 at 0.7 C; the sweep
+    adds 0.5 and 0.9 C and the fixed rate of 8,000 req/s."""
     from paper_2407_09333_amd import hb, workloads
 
     pool = workloads.serving_requests(pool_size, 1.0, seed=5)
     srv = hb.Server(hbm_budget_bytes=64 << 30, max_slots=1024)
     for r in pool[:16]:  # warm-up
         srv.wait(srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos))
-    # capacity: a saturating burst long enough (cap_burst requests, the pool cycled) that
-    # the pipeline's fill and drain are a small part of it
     t0 = srv.now()
     burst = [pool[k % pool_size] for k in range(cap_burst)]
     ts = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in burst]
-    t_sub = srv.now() - t0
     for t in ts:
         srv.wait(t)
     t1 = max(srv.times(t)["done"] for t in ts)
-    cap_rps = len(burst) / (t1 - t0)
-    cap_bytes = sum(int(r.lengths.sum()) for r in burst) / (t1 - t0)
-    print(f"bench: serving capacity {cap_rps:.0f} req/s ({cap_bytes / 1e9:.2f} GB/s), "
-          f"burst of {cap_burst} submitted in {t_sub * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    for t in ts:
+        srv.release(t)
+    burst_rps = len(burst) / (t1 - t0)
+    mean_bytes = float(np.mean([int(r.lengths.sum()) for r in pool]))
+    print(f"bench: serving burst capacity {burst_rps:.0f} req/s", file=sys.stderr, flush=True)
+    # bisection for the open-loop capacity
+    lo, hi = 0.25 * burst_rps, 1.1 * burst_rps
+    trials = []
+    run = _serve_open_loop(srv, pool, lo, int(max(lo * trial_s, 300)), seed=201)
+    trials.append(run)
+    if not _sustained(run):
+        hi = lo
+    for it in range(5):
+        if hi <= lo * 1.03:
+            break
+        mid = 0.5 * (lo + hi)
+        run = _serve_open_loop(srv, pool, mid, int(max(mid * trial_s, 300)), seed=202 + it)
+        trials.append(run)
+        print(f"bench: serving trial {mid:.0f} req/s: achieved {run['achieved_req_per_s']:.0f}, "
+              f"p99 {run['p99_ms']} ms", file=sys.stderr, flush=True)
+        if _sustained(run):
+            lo = mid
+        else:
+            hi = mid
+    cap_rps = lo
     runs = []
-    for frac in (None,) + tuple(fractions):
+    for frac in (0.7,) + tuple(f for f in fractions if f != 0.7) + (None,):
         rate = SERVE_FIXED_RATE if frac is None else frac * cap_rps
         n_req = int(min(max(rate * seconds / (len(fractions) + 1), 200), 30_000))
-        arrivals = np.cumsum(np.random.default_rng(105).exponential(1.0 / rate, size=n_req))
-        tickets, sched = [None] * n_req, np.zeros(n_req)
-        s0 = srv.stats()
-        start = srv.now() + 0.05
-        payload = 0
-        for k in range(n_req):
-            r = pool[k % pool_size]
-            target = start + arrivals[k]
-            while True:
-                d = target - srv.now()
-                if d <= 0:
-                    break
-                if d > 0.002:
-                    time.sleep(d - 0.001)
-            sched[k] = target
-            tickets[k] = srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)
-            payload += int(r.lengths.sum())
-        lat = np.zeros(n_req)
-        phases = np.zeros((n_req, 3))
-        parts = np.zeros((n_req, len(SERVE_PARTS)))
-        done_max = 0.0
-        for k, t in enumerate(tickets):
-            srv.wait(t)
-            tm = srv.trace(t)
-            lat[k] = tm["done"] - sched[k]
-            phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
-            # a step may be enqueued before its inputs' copy completes (the device then waits
-            # for the copy), so after stage_end the copy and the step launch run side by
-            # side: batch_wait counts only the time after the copy landed until the step was
-            # enqueued, exec_wait from the later of the two until the step began
-            ready = max(tm["launch"], tm["h2d_done"])
-            parts[k] = (tm["admit"] - sched[k], tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
-                        tm["h2d_done"] - tm["stage_end"], ready - tm["h2d_done"],
-                        tm["exec_begin"] - ready, tm["exec_end"] - tm["exec_begin"],
-                        tm["done"] - tm["exec_end"])
-            done_max = max(done_max, tm["done"])
-            srv.release(t)
-        s1 = srv.stats()
-        runs.append({"load_fraction": frac, "offered_req_per_s": round(rate, 1), "requests": n_req,
-                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "p999_ms": round(float(np.percentile(lat, 99.9)) * 1e3, 3),
-                     "achieved_GBps": round(payload / (done_max - start) / 1e9, 3),
-                     "steps": s1["steps"] - s0["steps"], "admission_stalls": s1["stalls"] - s0["stalls"],
-                     "median_ms_queue_staging_device": [round(float(x) * 1e3, 3) for x in np.median(phases, 0)],
-                     "p99_ms_queue_staging_device": [round(float(x) * 1e3, 3)
-                                                     for x in np.percentile(phases, 99, axis=0)],
-                     "parts_ms": {name: [round(float(np.percentile(parts[:, j], q)) * 1e3, 3) for q in (50, 99)]
-                                  for j, name in enumerate(SERVE_PARTS)}})
+        run = _serve_open_loop(srv, pool, rate, n_req)
+        run["load_fraction"] = frac
+        runs.append(run)
         where = f"{rate:.0f} req/s" if frac is None else f"{frac} C"
-        print(f"bench: serving at {where}: p50 {runs[-1]['p50_ms']} ms p99 {runs[-1]['p99_ms']} ms",
+        print(f"bench: serving at {where}: p50 {run['p50_ms']} ms p99 {run['p99_ms']} ms",
               file=sys.stderr, flush=True)
     peak = srv.stats()["peak_bytes"]
     srv.close()
     overload = None if getattr(args, "no_overload", False) else bench_serve_overload(pool)
-    head = runs[0]  # the fixed offered rate
+    head = runs[0]  # 0.7 C
     return {
         "workload": "Poisson arrivals; 1..10,000 messages per request (log-uniform), algorithm uniform, "
                     "lengths log-normal (median 256 B, sigma 1.5, cap 64 KiB); payload in host memory "
                     "(PCIe- and host-copy-inclusive); device budget 64 GiB",
-        "capacity_req_per_s": round(cap_rps, 1), "capacity_GBps": round(cap_bytes / 1e9, 3),
-        "headline": f"p50 / p99 at the fixed offered rate of {SERVE_FIXED_RATE:.0f} req/s (sweep[0]); the "
-                    "other sweep entries are fractions of the burst capacity C, which varies run to run",
+        "capacity_req_per_s": round(cap_rps, 1), "capacity_GBps": round(cap_rps * mean_bytes / 1e9, 3),
+        "capacity_rule": f"highest open-loop Poisson rate with achieved >= {SERVE_TRACK_FRAC} x offered and "
+                         f"p99 <= {SERVE_P99_BOUND_MS} ms (bisection over {trial_s} s trials)",
+        "capacity_trials": [{k: t[k] for k in ("offered_req_per_s", "achieved_req_per_s", "p99_ms")}
+                            for t in trials],
+        "burst_capacity_req_per_s": round(burst_rps, 1),
+        "headline": "p50 / p99 at 0.7 C (sweep[0]), C the open-loop capacity; the sweep also has 0.5 and "
+                    f"0.9 C and the fixed rate of {SERVE_FIXED_RATE:.0f} req/s",
         "offered_req_per_s": head["offered_req_per_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "p999_ms": head["p999_ms"], "achieved_GBps": head["achieved_GBps"],
         "sweep": runs, "peak_resident_bytes": peak, "overload": overload,
+        "inputs": _inputs_record(args, "serving_pool",
+                                 lengths=np.concatenate([r.lengths for r in pool]),
+                                 algos=np.concatenate([np.full(r.lengths.size, r.algo, np.int8) if r.algos is None
+                                                       else r.algos.astype(np.int8) for r in pool]),
+                                 counts=np.array([r.lengths.size for r in pool], np.int64)),
     }
 
 
@@ -722,6 +841,8 @@ def bench_serve_child(args):
            "--hw-queues", str(args.serve_hw_queues), "--serve-seconds", str(args.serve_seconds)]
     if args.no_overload:
         cmd.append("--no-overload")
+    if args.save_inputs:
+        cmd += ["--save-inputs", args.save_inputs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
     if r.returncode != 0:
         raise RuntimeError(f"serving child process failed with status {r.returncode}")

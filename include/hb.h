@@ -190,10 +190,21 @@ int hb_plan_run(hb_plan *plan, const uint8_t *algos, int algo, const uint8_t *me
                 const uint64_t *offsets, const uint64_t *lengths, uint64_t n,
                 uint8_t *digests_out, void *stream);
 
-/* Launch choices of a plan (after autotuning, if enabled). */
+/* Launch choices of a plan (after autotuning, if enabled): persistent-kernel waves per CU,
+ * messages per lane per work item, and the message-load scheme `variant`:
+ *   0  whole blocks in bursts of the default depth (MD5 four, SHA-1 / SM3 two) -- default
+ *   1  SHA-1 / SM3 one block at a time with the next block's loads in flight; MD5 as 0
+ *   2  one block per load
+ *   3  bursts of two whole blocks for every algorithm
+ *   4  bursts of four whole blocks for every algorithm
+ * With HB_PLAN_AUTOTUNE the first run times waves per CU {8, 16, 32} x messages per lane
+ * {1, 2} x the five schemes on its own input and keeps the fastest, cached per device, CU
+ * count, algorithm mix and length bucket (mean block count and spread, read from the
+ * plan's histogram); HB_TUNE_CACHE names a file that keeps the cache across processes. */
 int hb_plan_config(const hb_plan *plan, int *waves_per_cu, int *msgs_per_lane, int *variant);
 
-/* Force launch choices (0 keeps the current value); drops any captured graph. */
+/* Force launch choices (0 keeps the current waves per CU / messages per lane; variant is
+ * set as given, 0..4); drops any captured graph.  HB_EINVAL outside those ranges. */
 int hb_plan_set_config(hb_plan *plan, int waves_per_cu, int msgs_per_lane, int variant);
 
 /* Average duration in milliseconds of the persistent hashing kernel over the runs since

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hb_md5_table.hpp"
+
 namespace hb {
 
 enum : int { MD5 = 0, SHA1 = 1, SM3 = 2 };
@@ -85,15 +87,7 @@ __device__ __forceinline__ void md5_init(uint32_t s[8])
 // (a,b,c,d) <- (d,a,b,c); Fn / k / s as in the RFC's four rounds.
 __device__ __forceinline__ void md5_compress(uint32_t s[8], const uint32_t X[16])
 {
-    constexpr uint32_t T[64] = {
-        0xd76aa478, 0xe8c7b756, 0x242070db, 0xc1bdceee, 0xf57c0faf, 0x4787c62a, 0xa8304613, 0xfd469501,
-        0x698098d8, 0x8b44f7af, 0xffff5bb1, 0x895cd7be, 0x6b901122, 0xfd987193, 0xa679438e, 0x49b40821,
-        0xf61e2562, 0xc040b340, 0x265e5a51, 0xe9b6c7aa, 0xd62f105d, 0x02441453, 0xd8a1e681, 0xe7d3fbc8,
-        0x21e1cde6, 0xc33707d6, 0xf4d50d87, 0x455a14ed, 0xa9e3e905, 0xfcefa3f8, 0x676f02d9, 0x8d2a4c8a,
-        0xfffa3942, 0x8771f681, 0x6d9d6122, 0xfde5380c, 0xa4beea44, 0x4bdecfa9, 0xf6bb4b60, 0xbebfbc70,
-        0x289b7ec6, 0xeaa127fa, 0xd4ef3085, 0x04881d05, 0xd9d4d039, 0xe6db99e5, 0x1fa27cf8, 0xc4ac5665,
-        0xf4292244, 0x432aff97, 0xab9423a7, 0xfc93a039, 0x655b59c3, 0x8f0ccc92, 0xffeff47d, 0x85845dd1,
-        0x6fa87e4f, 0xfe2ce6e0, 0xa3014314, 0x4e0811a1, 0xf7537e82, 0xbd3af235, 0x2ad7d2bb, 0xeb86d391};
+    constexpr const uint32_t *T = kMd5T;
     uint32_t a = s[0], b = s[1], c = s[2], d = s[3];
 #define HB_MD5_STEP(TTF, k, sh, i)                                           \
     {                                                                        \
@@ -374,13 +368,19 @@ __device__ __forceinline__ void load_any_block(const Msg &m, uint64_t blk, bool 
     }
 }
 
+// Whole blocks read per burst by default: MD5 does the least work per byte, so it reads
+// four (two whole 128-byte L2 lines per lane); SHA-1 and SM3 two (one line).
+template <int A> constexpr int kDefaultBurst = A == MD5 ? 4 : 2;
+
 // Absorb the piece m into the chaining value s: its floor(L / 64) whole blocks are read
-// directly; with PAD the remaining one or two blocks of nb = floor((L + 8) / 64) + 1 --
-// tail bytes, 0x80, zeros and the length field m.bits -- are assembled in registers.
-// When every lane of a wave has the same length the loop and its branch are wave-uniform.
-template <int A, bool PAD>
+// directly, up to BURST (1, 2 or 4) per burst; with PAD the remaining one or two blocks of
+// nb = floor((L + 8) / 64) + 1 -- tail bytes, 0x80, zeros and the length field m.bits --
+// are assembled in registers.  When every lane of a wave has the same length the loop and
+// its branch are wave-uniform.
+template <int A, bool PAD, int BURST = kDefaultBurst<A>>
 __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
 {
+    static_assert(BURST == 1 || BURST == 2 || BURST == 4, "blocks per burst");
     const uint64_t nfast = m.len / 64u;
     const uint64_t nb = PAD ? (m.len + 8u) / 64u + 1u : nfast;
     // Bursts stop at nb - 2 blocks: every lane's first nb - 2 blocks are whole (nfast is
@@ -395,30 +395,25 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
         if (__all(nfast == nf_lead)) nburst = nfast;
     }
     uint64_t blk = 0;
-    if constexpr (A == MD5) {
-        // MD5 does the least work per byte, so memory bounds it: whole blocks go four (then
-        // two) at a time, whole 128-byte L2 lines per lane per burst.
-        const bool aligned = __ballot(m.r != 0) == 0;
+    // bursts of whole blocks (four, then two), so both halves of each 128-byte line are read
+    // before it can be evicted; little-endian words of dword-aligned messages (every lane of
+    // the wave) need no realignment
+    constexpr bool kBE = Traits<A>::kBE;
+    const bool aligned = !kBE && __ballot(m.r != 0) == 0;
+    if constexpr (BURST >= 4) {
         for (; blk + 4 <= nburst; blk += 4) {
             uint32_t w[4][16];
-            load_full_quad<false>(m, blk, aligned, w);
+            load_full_quad<kBE>(m, blk, aligned, w);
             compress<A>(s, w[0]);
             compress<A>(s, w[1]);
             compress<A>(s, w[2]);
             compress<A>(s, w[3]);
         }
+    }
+    if constexpr (BURST >= 2) {
         for (; blk + 2 <= nburst; blk += 2) {
             uint32_t w0[16], w1[16];
-            load_full_pair<false>(m, blk, aligned, w0, w1);
-            compress<A>(s, w0);
-            compress<A>(s, w1);
-        }
-    } else {
-        // SHA-1 / SM3: two whole blocks per burst, so both halves of a 128-byte line are
-        // read before it can be evicted
-        for (; blk + 2 <= nburst; blk += 2) {
-            uint32_t w0[16], w1[16];
-            load_full_pair<true>(m, blk, false, w0, w1);
+            load_full_pair<kBE>(m, blk, aligned, w0, w1);
             compress<A>(s, w0);
             compress<A>(s, w1);
         }
@@ -433,12 +428,12 @@ __device__ __forceinline__ void absorb(const Msg &m, uint32_t s[8])
 
 // Digest state of one whole message: the initial value, then every block including the
 // padding.
-template <int A>
+template <int A, int BURST = kDefaultBurst<A>>
 __device__ __forceinline__ void hash_message(const uint8_t *base, uint64_t len, uint32_t s[8])
 {
     const Msg m = make_msg<A>(base, len);
     init_state<A>(s);
-    absorb<A, true>(m, s);
+    absorb<A, true, BURST>(m, s);
 }
 
 // As hash_message, with the next whole block's loads issued before the current block is

@@ -1,5 +1,6 @@
 // hb_kernels.hip -- plain batch-hashing kernels: one lane per message, in index order.
 #include <algorithm>
+#include <cstdlib>
 
 #include "hb_device.hpp"
 #include "hb_internal.hpp"
@@ -7,6 +8,19 @@
 namespace hb {
 
 constexpr int kPlainBlock = 256;
+
+// Workgroups are dealt round-robin to the GPU's XCDs (8 on MI355X, each with its own L2);
+// renumbering them so that each XCD takes a contiguous run of the grid makes each XCD
+// stream through one contiguous region of the input.  Measured on 2^20 x 1 KiB MD5: 205 us
+// against 210 us in dispatch order; a load-only stream: 5.7 against 5.4 TB/s.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_contiguous_block()
+{
+    const uint32_t b = blockIdx.x, full = gridDim.x & ~(kXcds - 1u);
+    if (b >= full) return b;  // the last gridDim % 8 workgroups keep their number
+    return (b % kXcds) * (full / kXcds) + b / kXcds;
+}
 
 // Lane i hashes message i.  FIXED: message i starts at i * fixed_len and is fixed_len
 // bytes long (no metadata reads).  With `filter`, messages whose id differs from A are
@@ -19,7 +33,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(const uint8_t *__restrict
                                                        uint32_t stride,
                                                        const uint8_t *__restrict__ filter)
 {
-    const uint64_t i = uint64_t(blockIdx.x) * kPlainBlock + threadIdx.x;
+    const uint64_t i = uint64_t(xcd_contiguous_block()) * kPlainBlock + threadIdx.x;
     if (i >= n) return;
     if (filter) {
         const uint8_t id = filter[i];
@@ -37,6 +51,72 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(const uint8_t *__restrict
     uint32_t s[8];
     hash_message<A>(msgs + off, len, s);
     store_digest<A>(out + i * stride, s, stride);
+}
+
+// Fixed-length batch with message words staged through LDS (opt-in, HB_PLAIN_LDS=1).  Each
+// wave owns 64 consecutive messages.  Two whole blocks of all 64 go per burst: eight
+// 16-byte loads per lane, lane (q, p) of load j taking chunk p ^ q of message 8j + q, so
+// each load instruction reads eight whole 128-byte lines; the chunks are written to the
+// wave's LDS slice in that order and each lane reads back its own message's 128 bytes, the
+// XOR swizzle putting eight consecutive lanes on eight different bank groups.  The next
+// burst's loads are in flight while the current one is compressed.  Messages must start on
+// a dword (msgs and msg_len 4-byte aligned); the last one or two blocks and a partial last
+// wave go through the per-lane path.  Measured on 2^20 x 1 KiB MD5: 4x fewer L1 accesses,
+// read traffic 1.00x the payload, VALU busy 0.86 against 0.76, but the same time within 1 %:
+// the kernel runs at the HBM read rate either way.
+template <int A>
+__global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
+                                                           uint64_t len, uint8_t *__restrict__ out)
+{
+    __shared__ u32x4 slice[kPlainBlock / 64][512];  // per wave: 64 messages x 128 bytes
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u), lane = threadIdx.x % 64u;
+    const uint64_t m0 = (uint64_t(xcd_contiguous_block()) * (kPlainBlock / 64) + wave) * 64u;
+    if (m0 >= n) return;
+    const uint32_t q = lane / 8u, p = lane % 8u, sw = lane & 7u;
+    const uint32_t voff = uint32_t(q * len + (p ^ q) * 16u);  // load j adds 8 j len
+    const uint64_t nb = (len + 8u) / 64u + 1u, nfast = len / 64u;
+    const uint64_t nburst = m0 + 64u <= n ? nfast / 2u : 0u;  // wave-uniform
+    const uint8_t *wbase = msgs + m0 * len;
+    u32x4 *mine = slice[wave];
+    uint32_t s[8];
+    init_state<A>(s);
+    u32x4 pre[8];
+    auto load = [&](uint64_t k) {
+        const uint8_t *bk = wbase + k * 128u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            pre[j] = *reinterpret_cast<const HB_GLOBAL u32x4 *>(
+                reinterpret_cast<uintptr_t>(bk + (voff + uint32_t(8 * j) * uint32_t(len))));
+    };
+    if (nburst) load(0);
+    for (uint64_t k = 0; k < nburst; ++k) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) mine[j * 64 + lane] = pre[j];
+        if (k + 1 < nburst) load(k + 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t w[16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const u32x4 v = mine[lane * 8u + ((4u * h + i) ^ sw)];
+                w[4 * i] = v.x; w[4 * i + 1] = v.y; w[4 * i + 2] = v.z; w[4 * i + 3] = v.w;
+            }
+            if (Traits<A>::kBE)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) w[i] = bswap32(w[i]);
+            compress<A>(s, w);
+        }
+    }
+    const uint64_t mi = m0 + lane;
+    if (mi >= n) return;
+    const Msg m = make_msg<A>(msgs + mi * len, len);
+    for (uint64_t blk = nburst * 2u; blk < nb; ++blk) {
+        uint32_t w[16];
+        if (blk < nfast) load_full_block(m, blk, w);
+        else load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
+        compress<A>(s, w);
+    }
+    store_digest<A>(out + mi * Traits<A>::kDigest, s, Traits<A>::kDigest);
 }
 
 // The paper's workload (Sec. V-A.2): message i is the 9-character decimal text of
@@ -137,10 +217,36 @@ static hipError_t launch_a(const uint8_t *msgs, const uint64_t *offs, const uint
     return hipGetLastError();
 }
 
+template <int A>
+static hipError_t launch_lds_a(const uint8_t *msgs, uint64_t n, uint64_t len, uint8_t *out, hipStream_t stream)
+{
+    const uint64_t blocks = (n + kPlainBlock - 1) / kPlainBlock;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_plain_lds<A>, dim3(uint32_t(blocks)), dim3(kPlainBlock), 0, stream, msgs, n, len, out);
+    return hipGetLastError();
+}
+
+bool plain_lds_applies(const uint8_t *msgs, uint64_t fixed_len, uint32_t stride, int algo)
+{
+    const char *v = std::getenv("HB_PLAIN_LDS");
+    if (!v || std::atoi(v) == 0) return false;
+    // dword-aligned messages; 64 messages' offsets fit the loads' 32-bit offsets; packed digests
+    return (reinterpret_cast<uintptr_t>(msgs) & 3u) == 0 && fixed_len % 4u == 0 && fixed_len > 0 &&
+           fixed_len < (1ull << 25) && stride == uint32_t(digest_size(algo));
+}
+
 hipError_t launch_plain(int algo, const uint8_t *msgs, const uint64_t *offs, const uint64_t *lens,
                         uint64_t n, bool fixed, uint64_t fixed_len, uint8_t *out, uint32_t stride,
                         const uint8_t *filter, hipStream_t stream)
 {
+    if (fixed && !filter && plain_lds_applies(msgs, fixed_len, stride, algo)) {
+        switch (algo) {
+        case MD5: return launch_lds_a<MD5>(msgs, n, fixed_len, out, stream);
+        case SHA1: return launch_lds_a<SHA1>(msgs, n, fixed_len, out, stream);
+        case SM3: return launch_lds_a<SM3>(msgs, n, fixed_len, out, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (algo) {
     case MD5: return launch_a<MD5>(msgs, offs, lens, n, fixed, fixed_len, out, stride, filter, stream);
     case SHA1: return launch_a<SHA1>(msgs, offs, lens, n, fixed, fixed_len, out, stride, filter, stream);

@@ -632,22 +632,34 @@ __global__ __launch_bounds__(kThreads) void k_hash_long(PlanWs ws)
     long_lane<SCHED>(ws, blockIdx.x * kThreads + threadIdx.x);
 }
 
-template <int A, int PF>
+// Message-load schemes of the persistent kernel (the plan's "variant", a tuned choice):
+//   0  whole blocks in bursts of the default depth (MD5 four, SHA-1 / SM3 two)
+//   1  SHA-1 / SM3: one block at a time with the next block's loads in flight during the
+//      current compression; MD5 as 0
+//   2  one block per load (no bursts)
+//   3  bursts of two blocks for every algorithm
+//   4  bursts of four blocks for every algorithm
+constexpr int kLoadSchemes = 5;
+
+template <int V, int A>
+constexpr int scheme_burst() { return V == 2 ? 1 : (V == 3 ? 2 : (V == 4 ? 4 : kDefaultBurst<A>)); }
+
+template <int A, int V>
 __device__ __forceinline__ void hash_lane(const PlanDesc &d, uint32_t idx)
 {
     uint32_t s[8];
     const uint64_t off = reinterpret_cast<const HB_GLOBAL uint64_t *>(reinterpret_cast<uintptr_t>(d.offs))[idx];
     const uint64_t len = reinterpret_cast<const HB_GLOBAL uint64_t *>(reinterpret_cast<uintptr_t>(d.lens))[idx];
-    if constexpr (PF && A != MD5) hash_message_prefetch<A>(d.msgs + off, len, s);
-    else hash_message<A>(d.msgs + off, len, s);
+    if constexpr (V == 1 && A != MD5) hash_message_prefetch<A>(d.msgs + off, len, s);
+    else hash_message<A, scheme_burst<V, A>()>(d.msgs + off, len, s);
     store_digest<A>(d.out + uint64_t(idx) * d.stride, s, d.stride);
 }
 
 // Persistent fused kernel: each wave takes items from the queue until none are left.
 // An item is 64 * mpl sorted positions of one algorithm; lane l hashes positions
 // l, l + 64, ... of it.  Items whose cost exceeds the average per-wave share run at raised
-// wave priority so the longest chains keep their issue slots.  PF = 1 prefetches the next
-// block of SHA-1 / SM3 messages (MD5 already reads two blocks per burst).
+// wave priority so the longest chains keep their issue slots.  PF is the load scheme (see
+// kLoadSchemes).
 template <int PF>
 __device__ __forceinline__ void persistent_wave(const PlanWs &ws, uint32_t block, uint32_t nblocks)
 {
@@ -746,7 +758,7 @@ static std::map<TuneKey, TuneChoice> g_tune_cache;
 static bool g_tune_loaded = false;
 
 // Optional persistence: HB_TUNE_CACHE names a text file of lines
-// "arch cus algo_mask bucket waves_per_cu msgs_per_lane variant".
+// "arch cus algo_mask length_bucket waves_per_cu msgs_per_lane variant".
 static void load_tune_cache()
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -759,7 +771,7 @@ static void load_tune_cache()
     char arch[64];
     int cus, mask, bucket, w, m, v;
     while (std::fscanf(f, "%63s %d %d %d %d %d %d", arch, &cus, &mask, &bucket, &w, &m, &v) == 7)
-        if (w > 0 && w <= 64 && m > 0 && m <= kMaxMpl && (v == 0 || v == 1))
+        if (w > 0 && w <= 64 && m > 0 && m <= kMaxMpl && v >= 0 && v < kLoadSchemes)
             g_tune_cache[TuneKey{arch, cus, mask, bucket}] = TuneChoice{w, m, v};
     std::fclose(f);
 }
@@ -789,6 +801,7 @@ struct hb_plan {
     int mpl = 1;
     int variant = 0;
     bool tuned = false;
+    int tune_bucket = -1;           // length bucket the autotuner keyed its choice by
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -846,6 +859,35 @@ static void collect_timing(hb_plan *p, bool wait)
     p->ev_pending.swap(keep);
 }
 
+template <int V>
+static void launch_fused_v(bool sched, dim3 grid, hipStream_t s, const PlanWs &ws, uint32_t long_blocks)
+{
+    if (sched) hipLaunchKernelGGL((k_hash_fused<1, V>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+    else hipLaunchKernelGGL((k_hash_fused<0, V>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+}
+
+static void launch_fused(bool sched, int variant, dim3 grid, hipStream_t s, const PlanWs &ws, uint32_t long_blocks)
+{
+    switch (variant) {
+    case 1: launch_fused_v<1>(sched, grid, s, ws, long_blocks); break;
+    case 2: launch_fused_v<2>(sched, grid, s, ws, long_blocks); break;
+    case 3: launch_fused_v<3>(sched, grid, s, ws, long_blocks); break;
+    case 4: launch_fused_v<4>(sched, grid, s, ws, long_blocks); break;
+    default: launch_fused_v<0>(sched, grid, s, ws, long_blocks); break;
+    }
+}
+
+static void launch_persistent(int variant, dim3 grid, hipStream_t s, const PlanWs &ws)
+{
+    switch (variant) {
+    case 1: hipLaunchKernelGGL(k_hash_persistent<1>, grid, dim3(kThreads), 0, s, ws); break;
+    case 2: hipLaunchKernelGGL(k_hash_persistent<2>, grid, dim3(kThreads), 0, s, ws); break;
+    case 3: hipLaunchKernelGGL(k_hash_persistent<3>, grid, dim3(kThreads), 0, s, ws); break;
+    case 4: hipLaunchKernelGGL(k_hash_persistent<4>, grid, dim3(kThreads), 0, s, ws); break;
+    default: hipLaunchKernelGGL(k_hash_persistent<0>, grid, dim3(kThreads), 0, s, ws); break;
+    }
+}
+
 // Enqueue the pipeline (after k_set_desc) on stream s.  With `timed`, HIP events on s
 // bracket the persistent hashing kernel.
 static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
@@ -872,14 +914,7 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         const uint32_t long_blocks =
             uint32_t((uint64_t(ws.max_long_waves + ws.max_direct_waves) * 64u + kThreads - 1) / kThreads);
         const dim3 grid{long_blocks + uint32_t(hash_blocks), 1, 1};
-        if (p->long_sched && p->variant == 1)
-            hipLaunchKernelGGL((k_hash_fused<1, 1>), grid, dim3(kThreads), 0, s, ws, long_blocks);
-        else if (p->long_sched)
-            hipLaunchKernelGGL((k_hash_fused<1, 0>), grid, dim3(kThreads), 0, s, ws, long_blocks);
-        else if (p->variant == 1)
-            hipLaunchKernelGGL((k_hash_fused<0, 1>), grid, dim3(kThreads), 0, s, ws, long_blocks);
-        else
-            hipLaunchKernelGGL((k_hash_fused<0, 0>), grid, dim3(kThreads), 0, s, ws, long_blocks);
+        launch_fused(p->long_sched, p->variant, grid, s, ws, long_blocks);
     } else if (p->long_on) {
         // fork: the long chains start first on the side stream and run beside the bulk.  A
         // failed fork or join is returned: unjoined, the run's stream could report the
@@ -895,8 +930,7 @@ static hipError_t enqueue_pipeline(hb_plan *p, hipStream_t s, bool timed)
         if ((fe = hipEventRecord(p->ev_join, p->side)) != hipSuccess) return fe;
     }
     if (!fused) {
-        if (p->variant == 1) hipLaunchKernelGGL(k_hash_persistent<1>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
-        else hipLaunchKernelGGL(k_hash_persistent<0>, dim3(hash_blocks), dim3(kThreads), 0, s, ws);
+        launch_persistent(p->variant, dim3(hash_blocks), s, ws);
     }
     if (p->long_on && !fused) {  // join
         const hipError_t je = hipStreamWaitEvent(s, p->ev_join, 0);
@@ -939,12 +973,44 @@ static int launch_run(hb_plan *p, const PlanDesc &d, hipStream_t s)
     return HB_OK;
 }
 
-// Time each launch choice on this run's input and keep the fastest (cached per device,
-// algorithm mix and mean message length).
+// Length bucket of a batch, from the plan's own histogram of (algorithm, block count)
+// after a run: 16 x floor(log2(mean blocks per message)) + floor(log2(longest / mean)),
+// capped at 15.  Batches of equal mean length but very different spread (fixed lengths,
+// uniform, log-normal) land in different buckets.
+static int length_bucket(const hb_plan *p, hipStream_t s, int &bucket)
+{
+    std::vector<uint32_t> hist(3ull * kBins);
+    PlanMeta meta{};
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(hist.data(), p->ws.hist, hist.size() * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&meta, p->ws.meta, sizeof(meta), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_error(e, "hb_plan_run: autotune length bucket");
+    uint64_t count = 0, blocks = 0;
+    for (uint64_t k = 0; k < hist.size(); ++k) {
+        count += hist[k];
+        blocks += uint64_t(hist[k]) * (k % kBins);
+    }
+    const uint64_t mean = count ? std::max<uint64_t>(1, blocks / count) : 1;
+    const uint64_t longest = std::max<uint64_t>(meta.max_key, 1);
+    auto ilog2 = [](uint64_t x) { int r = 0; while (x > 1) { x >>= 1; ++r; } return r; };
+    bucket = 16 * ilog2(mean) + std::min(15, ilog2(longest / mean));
+    return HB_OK;
+}
+
+// Time each launch choice on this run's input and keep the fastest, cached per device,
+// algorithm mix and length bucket: waves per CU, messages per lane and the message-load
+// scheme (bursts of 1, 2 or 4 whole blocks, or next-block prefetch; kLoadSchemes).
 static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask)
 {
+    const int flags_saved = p->flags;
+    p->flags &= ~HB_PLAN_GRAPH;
+    // one run with the current choice fills the histogram that names the length bucket
+    PlanDesc d = d0;
+    d.mpl = p->mpl;
+    int rc = launch_run(p, d, s);
     TuneKey key{p->arch, p->cus, algo_mask, 0};
-    for (uint64_t m = d0.n; m > 1; m >>= 1) key.len_bucket++;  // bucket: log2 of the batch size
+    if (rc == HB_OK) rc = length_bucket(p, s, key.len_bucket);
+    if (rc != HB_OK) { p->flags = flags_saved; return rc; }
     load_tune_cache();
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
@@ -953,41 +1019,38 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
             p->waves_per_cu = it->second.waves_per_cu;
             p->mpl = it->second.mpl;
             p->variant = it->second.variant;
+            p->flags = flags_saved;
+            p->tune_bucket = key.len_bucket;
             return HB_OK;
         }
     }
-    const int flags_saved = p->flags;
-    p->flags &= ~HB_PLAN_GRAPH;
     float best = 1e30f;
     TuneChoice bestc{p->waves_per_cu, p->mpl, p->variant};
     const int wpcs[] = {8, 16, 32};
     const int mpls[] = {1, 2};
-    const int variants[] = {0, 1};
-    hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    for (int var : variants)
-    for (int mpl : mpls) {
-        for (int w : wpcs) {
-            p->waves_per_cu = w;
-            p->variant = var;
-            PlanDesc d = d0;
-            d.mpl = mpl;
-            p->mpl = mpl;
-            float tot = 0.f;
-            for (int rep = 0; rep < 2; ++rep) {
-                hipEventRecord(a, s);
-                int rc = launch_run(p, d, s);
-                hipEventRecord(b, s);
-                if (rc != HB_OK) { p->flags = flags_saved; hipEventDestroy(a); hipEventDestroy(b); return rc; }
-                hipEventSynchronize(b);
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, a, b);
-                if (rep) tot += ms;  // first repetition is a warm-up
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) { p->flags = flags_saved; return hip_error(e, "hb_plan_run: autotune events"); }
+    for (int var = 0; var < kLoadSchemes && rc == HB_OK; ++var)
+        for (int mpl : mpls)
+            for (int w : wpcs) {
+                p->waves_per_cu = w;
+                p->variant = var;
+                p->mpl = mpl;
+                d.mpl = mpl;
+                float tot = 0.f;
+                for (int rep = 0; rep < 2 && rc == HB_OK; ++rep) {
+                    hipEventRecord(a, s);
+                    rc = launch_run(p, d, s);
+                    hipEventRecord(b, s);
+                    hipEventSynchronize(b);
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, a, b);
+                    if (rep) tot += ms;  // first repetition is a warm-up
+                }
+                if (rc == HB_OK && tot < best) { best = tot; bestc = TuneChoice{w, mpl, var}; }
             }
-            if (tot < best) { best = tot; bestc = TuneChoice{w, mpl, var}; }
-        }
-    }
     hipEventDestroy(a);
     hipEventDestroy(b);
     collect_timing(p, true);
@@ -997,6 +1060,8 @@ static int autotune(hb_plan *p, const PlanDesc &d0, hipStream_t s, int algo_mask
     p->waves_per_cu = bestc.waves_per_cu;
     p->mpl = bestc.mpl;
     p->variant = bestc.variant;
+    p->tune_bucket = key.len_bucket;
+    if (rc != HB_OK) return rc;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = bestc;
@@ -1217,7 +1282,7 @@ int hb_plan_set_config(hb_plan *p, int waves_per_cu, int msgs_per_lane, int vari
 {
     if (!p) return set_error(HB_EINVAL, "hb_plan_set_config: null plan");
     if (waves_per_cu < 0 || waves_per_cu > 64 || msgs_per_lane < 0 || msgs_per_lane > kMaxMpl || variant < 0 ||
-        variant > 1)
+        variant >= kLoadSchemes)
         return set_error(HB_EINVAL, "hb_plan_set_config: out of range");
     if (waves_per_cu) p->waves_per_cu = waves_per_cu;
     if (msgs_per_lane) p->mpl = msgs_per_lane;

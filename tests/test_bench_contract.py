@@ -21,7 +21,9 @@ def test_roofline_constants():
 
     # 256 CUs x 64 lanes x 2.4 GHz
     assert abs(bench.ALU_PEAK_TOPS - 39.3216) < 1e-9
-    assert bench.OPS_PER_BLOCK == {"md5": 340, "sha1": 613, "sm3": 1348}
+    # the fused op-count floors per 64-byte block; MD5 needs no byte-order perms on the
+    # dword-aligned fixed-length batches the roofline is quoted on
+    assert bench.OPS_PER_BLOCK == {"md5": 324, "sha1": 613, "sm3": 1348}
 
 
 def test_critical_path_bound():

@@ -42,6 +42,23 @@ def test_fixed_lengths(hb, algo, L):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n,L", [(300, 1024), (640, 128), (1000, 4), (515, 132), (4096, 2048), (128, 1028),
+                                 (257, 256), (64, 60)])
+def test_fixed_lds_staged(hb, monkeypatch, algo, n, L):
+    """The LDS-staged fixed-length kernel (HB_PLAIN_LDS=1): whole waves stage two blocks per
+    burst through LDS, partial waves and the last blocks go per lane; digests bit-exact
+    against the oracle, and no write outside the digest buffer."""
+    monkeypatch.setenv("HB_PLAIN_LDS", "1")
+    b = workloads.fixed_batch(algo, n, L, seed=500 + L)
+    print(f"case fixed lds algo={algo} n={n} L={L}", flush=True)
+    ds = oracle.DIGEST_SIZE[algo]
+    buf, out = guarded_out(n, ds)
+    hb.hash_batch_fixed(algo, b.messages, n, L, out=out)
+    check_guard(buf, n, ds)
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), "fixed lds")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
 def test_every_length_0_to_300_packed(hb, algo):
     lens = np.arange(301, dtype=np.uint64)
     offs = workloads.packed(lens)

@@ -60,8 +60,12 @@ def test_plan_mixed_with_long_empty_and_invalid(hb, flags):
     plan.close()
 
 
-@pytest.mark.parametrize("wpc,mpl,var", [(4, 1, 0), (8, 2, 1), (16, 4, 0), (32, 1, 1), (64, 3, 1), (16, 2, 1)])
+@pytest.mark.parametrize("wpc,mpl,var", [(4, 1, 0), (8, 2, 1), (16, 4, 0), (32, 1, 1), (64, 3, 1), (16, 2, 1),
+                                         (8, 1, 2), (16, 2, 2), (32, 1, 3), (16, 3, 3), (8, 2, 4), (16, 1, 4)])
 def test_launch_choices_give_identical_digests(hb, wpc, mpl, var):
+    """Every launch choice the autotuner may pick -- waves per CU, messages per lane and the
+    message-load scheme (variant 0..4: default bursts, next-block prefetch, one block per
+    load, two- and four-block bursts) -- gives the oracle's digests."""
     msgs, offs, lens, algos = _batch_mixed_with_long(seed=7, total=1_000_000)
     print(f"case choices wpc={wpc} mpl={mpl} variant={var}", flush=True)
     plan = hb.Plan(offs.size, flags=0)
@@ -74,13 +78,43 @@ def test_launch_choices_give_identical_digests(hb, wpc, mpl, var):
     plan.close()
 
 
+def test_set_config_rejects_unknown_scheme(hb):
+    plan = hb.Plan(1000, flags=0)
+    with pytest.raises(hb.HBError) as ei:
+        plan.set_config(waves_per_cu=16, msgs_per_lane=1, variant=5)
+    assert ei.value.status == hb.HB_EINVAL
+    plan.close()
+
+
+def test_autotune_cache_keyed_by_length_bucket(hb, tmp_path, monkeypatch):
+    """The tuning cache file holds one line per (device, CUs, algorithm mix, length bucket):
+    a fixed-length and a uniform batch of the same size and algorithm get separate lines,
+    and a second plan on a batch of the same bucket reuses the cached choice."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HB_TUNE_CACHE", str(cache))
+    fixed = workloads.fixed_batch(2, 20_000, 1024, seed=51)
+    unif = workloads.uniform_lengths_batch(2, 20_000, 8192, seed=52)
+    cfgs = []
+    for b in (fixed, unif, workloads.fixed_batch(2, 20_000, 1024, seed=53)):
+        plan = hb.Plan(b.n, flags=hb.PLAN_GRAPH | hb.PLAN_AUTOTUNE)
+        got = plan.run(b.messages, b.offsets, b.lengths, algo=2).cpu().numpy()
+        assert_same(got, oracle.hash_batch(2, b.messages, b.offsets, b.lengths), "autotuned, bucketed cache")
+        cfgs.append(plan.config())
+        plan.close()
+    assert cfgs[2] == cfgs[0]  # same bucket: the cached choice
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+    buckets = {int(ln[3]) for ln in lines if ln[2] == "4"}  # algorithm mask 1 << SM3
+    assert len(buckets) >= 2, lines
+    assert all(int(ln[6]) in range(5) for ln in lines)
+
+
 def test_autotune_picks_a_valid_choice(hb):
     b = workloads.uniform_lengths_batch(2, 30_000, 4096, seed=14)
     print("case autotune", flush=True)
     plan = hb.Plan(30_000, flags=hb.PLAN_GRAPH | hb.PLAN_AUTOTUNE)
     got = plan.run(b.messages, b.offsets, b.lengths, algo=2).cpu().numpy()
     cfg = plan.config()
-    assert cfg["waves_per_cu"] in (8, 16, 32) and cfg["msgs_per_lane"] in (1, 2) and cfg["variant"] in (0, 1)
+    assert cfg["waves_per_cu"] in (8, 16, 32) and cfg["msgs_per_lane"] in (1, 2) and cfg["variant"] in range(5)
     assert_same(got, oracle.hash_batch(2, b.messages, b.offsets, b.lengths), "autotuned")
     plan.close()
 
@@ -189,7 +223,7 @@ def test_long_chain_direct_cap(hb, monkeypatch):
     print("case long path direct cap", flush=True)
     want = oracle.hash_batch(algos, msgs, offs, lens)
     for flags in (hb.PLAN_GRAPH, hb.PLAN_GRAPH | hb.PLAN_LONG_INLINE):
-        for var in (0, 1):
+        for var in range(5):
             plan = hb.Plan(n, flags=flags)
             plan.set_config(waves_per_cu=16, msgs_per_lane=1, variant=var)
             assert_same(plan.run(msgs, offs, lens, algos=algos).cpu().numpy(), want, f"direct cap {flags} {var}")
