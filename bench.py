@@ -85,6 +85,9 @@ def parse():
     p.add_argument("--hw-queues", type=int, default=None,
                    help="HIP hardware queues for this process (GPU_MAX_HW_QUEUES, at most 32); "
                         "default: the environment's (HIP's four), eight for --workload serve")
+    p.add_argument("--serve-mode", choices=("steps", "resident"), default=None,
+                   help="serving loop mode (HB_SERVER_MODE): device steps per batch, or one resident "
+                        "serving kernel that requests join; default: the library's")
     p.add_argument("--serve-hw-queues", type=int, default=SERVE_HW_QUEUES_DEFAULT,
                    help="hardware queues of the child process that measures serving in the full run")
     p.add_argument("--copy-calibration", action="store_true",
@@ -759,6 +762,9 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
     adds 0.5 and 0.9 C and the fixed rate of 8,000 req/s."""
     from paper_2407_09333_amd import hb, workloads
 
+    if getattr(args, "serve_mode", None):
+        os.environ["HB_SERVER_MODE"] = args.serve_mode
+    mode = os.environ.get("HB_SERVER_MODE", "steps")
     pool = workloads.serving_requests(pool_size, 1.0, seed=5)
     srv = hb.Server(hbm_budget_bytes=64 << 30, max_slots=1024)
     for r in pool[:16]:  # warm-up
@@ -812,6 +818,7 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
         "workload": "Poisson arrivals; 1..10,000 messages per request (log-uniform), algorithm uniform, "
                     "lengths log-normal (median 256 B, sigma 1.5, cap 64 KiB); payload in host memory "
                     "(PCIe- and host-copy-inclusive); device budget 64 GiB",
+        "mode": mode,
         "capacity_req_per_s": round(cap_rps, 1), "capacity_GBps": round(cap_rps * mean_bytes / 1e9, 3),
         "capacity_rule": f"highest open-loop Poisson rate with achieved >= {SERVE_TRACK_FRAC} x offered and "
                          f"p99 <= {SERVE_P99_BOUND_MS} ms (bisection over {trial_s} s trials)",
@@ -831,18 +838,21 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
     }
 
 
-def bench_serve_child(args):
+def bench_serve_child(args, mode=None, overload=True):
     """The serving section, measured in a child process with its own hardware-queue count
     (--serve-hw-queues), started before this process initialises the GPU; this process
-    waits for it."""
+    waits for it.  mode: the serving loop's mode (None: --serve-mode or the library's)."""
     import subprocess
 
     cmd = [sys.executable, "-u", str(Path(__file__).resolve()), "--workload", "serve",
            "--hw-queues", str(args.serve_hw_queues), "--serve-seconds", str(args.serve_seconds)]
-    if args.no_overload:
+    if args.no_overload or not overload:
         cmd.append("--no-overload")
     if args.save_inputs:
         cmd += ["--save-inputs", args.save_inputs]
+    mode = mode or args.serve_mode
+    if mode:
+        cmd += ["--serve-mode", mode]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
     if r.returncode != 0:
         raise RuntimeError(f"serving child process failed with status {r.returncode}")
@@ -900,6 +910,8 @@ def main():
         if not args.only_headline:
             print("bench: serving (child process)", file=sys.stderr, flush=True)
             serving = bench_serve_child(args)
+            print("bench: serving, resident kernel (child process)", file=sys.stderr, flush=True)
+            serving_resident = bench_serve_child(args, mode="resident", overload=False)
         rec = bench_fixed(args)
         rec["clock_note"] = _clock_ghz_note()
         if not args.only_headline:
@@ -914,6 +926,7 @@ def main():
             print("bench: incremental hashing", file=sys.stderr, flush=True)
             rec["incremental"] = bench_incremental(args)
             rec["serving"] = serving
+            rec["serving_resident"] = serving_resident
     elif args.workload == "uneven":
         rec = {"batched_uneven": bench_uneven(args, steps=args.steps, warmup=args.warmup)}
     elif args.workload == "mixed":

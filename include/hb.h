@@ -311,7 +311,17 @@ typedef struct hb_server hb_server;
  * HB_SERVER_COPY_STREAMS copy streams (default 1, or 2 with GPU_MAX_HW_QUEUES >= 8);
  * HB_SERVER_COPY=kernel copies payload by kernel from the rings' device mapping, not the
  * copy engine.  A request arriving while others run starts as soon as memory and a slot free up,
- * and its work overlaps theirs on the device.  Returns HB_EINVAL for a null server pointer,
+ * and its work overlaps theirs on the device.
+ * HB_SERVER_MODE=resident replaces the steps with one resident serving kernel that requests
+ * join while it runs: as soon as a request's payload has landed, its work items (up to 64
+ * messages of one algorithm, ordered by algorithm and block count) go into a ring in
+ * pinned host memory; the kernel's first wave copies them into device memory and its other
+ * waves claim them (several at once when a backlog has built up), hash them and write the
+ * digests and a done flag straight to pinned host memory.  The kernel leaves after 5 ms
+ * without items (HB_SERVER_RESIDENT_IDLE_MS) or when the server is destroyed, and the loop
+ * starts it again when items wait; one workgroup per CU (HB_SERVER_RESIDENT_WGS).  While it
+ * runs, device-wide synchronisations of the process (hipDeviceSynchronize, hipFree) wait
+ * for it.  Returns HB_EINVAL for a null server pointer,
  * a budget below 256 bytes or max_slots <= 0, HB_ENOMEM if the device arena or pinned
  * buffers cannot be allocated, HB_EHIP for other runtime failures.
  */

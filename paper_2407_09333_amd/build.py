@@ -18,7 +18,7 @@ ROOT = PKG.parent
 LIB = PKG / "libhb.so"
 OBJDIR = PKG / "_build"
 
-SOURCES = ["hb_api.cpp", "hb_kernels.hip", "hb_stream.hip", "hb_plan.hip", "hb_host.cpp", "hb_server.cpp",
+SOURCES = ["hb_api.cpp", "hb_kernels.hip", "hb_stream.hip", "hb_plan.hip", "hb_serve.hip", "hb_host.cpp", "hb_server.cpp",
            "hb_cpu.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -31,6 +31,12 @@ void cpu_hash_range(const uint8_t *algos, int algo, const uint8_t *msgs, const u
 // engine): device memory, or pinned host memory through its device mapping.
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream);
 
+struct ServeRings;
+
+// The resident serving kernel (hb_serve.hip): `workgroups` workgroups of 256 lanes, the
+// first wave dispatching, the rest hashing published items until told to stop or idle.
+hipError_t launch_serve(const ServeRings &rings, uint32_t gen, int workgroups, hipStream_t stream);
+
 // The paper's 9-digit decimal workload, generated on the device (see hash_digits9).
 hipError_t launch_digits9(int algo, uint64_t start, uint64_t n, uint8_t *out, hipStream_t stream);
 

@@ -15,8 +15,15 @@ namespace hb {
 // request overtakes another).  R needs `payload` and `arena_off` members; `on_admit(r)` is
 // called for each admitted request after its range is reserved.  Returns the number
 // admitted.
-template <class R, class F>
-size_t admit_in_order(std::deque<R *> &pending, Arena &arena, int &slots_used, int max_slots, F &&on_admit)
+// `take_more(r)` (optional) reserves any further resource the request needs after its arena
+// range; if it returns false the range is given back and admission stops there too.
+struct TakeNothing {
+    template <class R> bool operator()(R *) const { return true; }
+};
+
+template <class R, class F, class T = TakeNothing>
+size_t admit_in_order(std::deque<R *> &pending, Arena &arena, int &slots_used, int max_slots, F &&on_admit,
+                      T &&take_more = T())
 {
     size_t admitted = 0;
     while (!pending.empty() && slots_used < max_slots) {
@@ -25,6 +32,10 @@ size_t admit_in_order(std::deque<R *> &pending, Arena &arena, int &slots_used, i
         if (r->payload) {
             off = arena.alloc(r->payload);
             if (off == Arena::kFail) break;
+        }
+        if (!take_more(r)) {
+            if (r->payload) arena.release(off, r->payload);
+            break;
         }
         r->arena_off = off;
         ++slots_used;

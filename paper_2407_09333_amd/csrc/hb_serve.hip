@@ -1,0 +1,166 @@
+// hb_serve.hip -- the resident serving kernel: requests join the device work already running.
+//
+// The serving loop publishes work items (up to 64 messages of one algorithm each) into a
+// ring in pinned host memory as soon as a request's payload has landed in the device
+// arena.  One launch of k_serve stays resident while items keep coming: its first wave is
+// the dispatcher, which polls the host ring's tail over PCIe and copies new items into a
+// device-memory ring; every other wave claims items from that ring with a compare-and-swap
+// on the ring's head, hashes them (one lane per message, digests written straight to pinned
+// host memory) and sets the item's done flag there.  So a request that arrives while long
+// chains are being hashed starts on an idle wave at once instead of waiting for a step to
+// end.  Every wave's wait is bounded: the dispatcher stops the launch after idle_ticks
+// without a new item (or when the host sets its stop flag, or after max_ticks), every
+// worker leaves when told to, or on its own after twice the idle time; the host relaunches
+// when items are published and no launch is running.  Head and tail live in device memory
+// across launches, so items a finished launch did not take are taken by the next.
+#include "hb_device.hpp"
+#include "hb_internal.hpp"
+#include "hb_serve.hpp"
+
+namespace hb {
+
+constexpr int kServeThreads = 256;
+constexpr uint64_t kMaxClaim = 16;  // items one wave claims at once at most
+
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }  // 100 MHz
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// One item: lane l hashes message slot first + l.  The wave's 64 digests (32 bytes each,
+// canonical bytes, zero past the digest size) are gathered in LDS and written to the digest
+// ring's slots first .. first + count - 1 with whole 16-byte stores from consecutive lanes,
+// so the writes cross PCIe as whole lines rather than as 4-byte pieces; the loop reorders
+// them into the caller's order.  The item's algorithm is the same for every lane.
+template <int A>
+__device__ __forceinline__ void serve_lane(const ServeRings &R, uint32_t slot, uint32_t *mine)
+{
+    const uint64_t off = R.off[slot], len = R.len[slot];
+    uint32_t s[8];
+    if constexpr (A == MD5) hash_message<MD5>(R.arena + off, len, s);
+    else hash_message_prefetch<A>(R.arena + off, len, s);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        mine[q] = q < Traits<A>::kWords ? (Traits<A>::kBE ? bswap32(s[q]) : s[q]) : 0u;
+}
+
+__device__ __forceinline__ void serve_item(const ServeRings &R, const ServeItem &it, uint32_t lane, uint32_t *wave_lds)
+{
+    if (lane < it.count) {
+        uint32_t *mine = wave_lds + lane * 8u;
+        if (it.algo == MD5) serve_lane<MD5>(R, it.first + lane, mine);
+        else if (it.algo == SHA1) serve_lane<SHA1>(R, it.first + lane, mine);
+        else serve_lane<SM3>(R, it.first + lane, mine);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's LDS writes before its reads
+    const uint32_t chunks = it.count * 2u;  // 16-byte chunks of the item's digests
+    uint8_t *dst = R.digests + uint64_t(it.first) * 32u;
+    for (uint32_t c = lane; c < chunks; c += 64u) {
+        const uint32_t *src = wave_lds + c * 4u;
+        u32x4 v;
+        v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = src[3];
+        *reinterpret_cast<HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(dst + uint64_t(c) * 16u)) = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // reads done before the next item's writes
+}
+
+__global__ __launch_bounds__(kServeThreads) void k_serve(ServeRings R, uint32_t gen)
+{
+    __shared__ uint32_t digest_lds[kServeThreads / 64][64 * 8];  // per wave: 64 digests of 32 bytes
+    const uint32_t lane = __lane_id();
+    const uint64_t mask = R.items_cap - 1u;
+    const uint64_t t0 = now_ticks();
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        // dispatcher: host ring -> device ring
+        uint64_t dt = bcast64(lane == 0 ? __hip_atomic_load(R.d_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0);
+        uint64_t last = t0;
+        for (;;) {
+            const uint64_t now = now_ticks();
+            uint64_t ht = 0, head = 0;
+            uint32_t stop = 0;
+            // relaxed polls: an acquire here would invalidate this XCD's L2 on every poll
+            if (lane == 0) {
+                stop = __hip_atomic_load(R.h_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                ht = __hip_atomic_load(R.h_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                head = __hip_atomic_load(R.d_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            stop = __builtin_amdgcn_readfirstlane(stop);
+            ht = bcast64(ht);
+            head = bcast64(head);
+            if (ht > dt) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's item writes
+                for (uint64_t k = dt + lane; k < ht; k += 64) R.d_items[k & mask] = R.h_items[k & mask];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (lane == 0) __hip_atomic_store(R.d_tail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                dt = ht;
+                last = now;
+            } else if (head < dt) {
+                last = now;  // items still wait to be claimed
+            }
+            if (stop || now - last > R.idle_ticks || now - t0 > R.max_ticks) break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+        if (lane == 0) __hip_atomic_store(R.d_stop, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    // workers: an idle wave polls the device ring's tail and stop word every ~2 us (one
+    // lane, two relaxed loads: an acquire would invalidate the XCD's L2 on every poll), so a
+    // thousand idle waves cost little; the one acquire is made after an item is claimed
+    uint64_t last = t0;
+    for (;;) {
+        uint64_t h = 0, t = 0;
+        uint32_t stop = 0;
+        if (lane == 0) {
+            stop = __hip_atomic_load(R.d_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            t = __hip_atomic_load(R.d_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        stop = __builtin_amdgcn_readfirstlane(stop);
+        t = bcast64(t);
+        if (stop == gen) break;
+        if (lane == 0) h = __hip_atomic_load(R.d_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        h = bcast64(h);
+        if (h < t) {
+            // claim one item, or up to kMaxClaim when a backlog has built up: the acquire
+            // and release below are cache-wide operations of the XCD's L2, and under load
+            // they, not the hashing, bound the items per second
+            const uint64_t backlog = t - h;
+            const uint64_t take = backlog >= 32u * kMaxClaim ? kMaxClaim : (backlog >= 64u ? backlog / 32u : 1u);
+            uint32_t won = 0;
+            if (lane == 0)
+                won = __hip_atomic_compare_exchange_strong(R.d_head, &h, h + take, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                          ? 1u
+                          : 0u;
+            if (!__builtin_amdgcn_readfirstlane(won)) continue;  // another wave moved the head
+            // see the message slots the host wrote and the payload the copy engine wrote
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            for (uint64_t k = 0; k < take; ++k) {
+                const ServeItem it = R.d_items[(h + k) & mask];
+                serve_item(R, it, lane, digest_lds[threadIdx.x / 64u]);
+            }
+            // digests visible to the host before the items' done flags
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            if (lane < take)
+                __hip_atomic_store(R.done + ((h + lane) & mask), uint32_t(h + lane + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            last = now_ticks();
+            continue;
+        }
+        const uint64_t now = now_ticks();
+        if (now - last > 2 * R.idle_ticks || now - t0 > R.max_ticks) break;  // bounded even without the dispatcher
+        __builtin_amdgcn_s_sleep(64);
+    }
+}
+
+hipError_t launch_serve(const ServeRings &rings, uint32_t gen, int workgroups, hipStream_t stream)
+{
+    if (workgroups < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_serve, dim3(uint32_t(workgroups)), dim3(kServeThreads), 0, stream, rings, gen);
+    return hipGetLastError();
+}
+
+}  // namespace hb

@@ -35,6 +35,7 @@
 #include "hb_internal.hpp"
 #include "hb_outcome.hpp"
 #include "hb_policy.hpp"
+#include "hb_serve.hpp"
 #include "hb_stage.hpp"
 
 namespace hb {
@@ -56,6 +57,11 @@ constexpr uint64_t kRing = 64ull << 20;        // pinned staging ring per stagin
 constexpr size_t kMaxGroup = 256;              // requests staged together at most
 constexpr size_t kMaxInflight = 64;            // copies in flight per staging thread at most
 constexpr int kCopyStreams = 2;                // copy streams at most
+// resident mode (HB_SERVER_MODE=resident): one resident launch takes published work items
+constexpr uint64_t kResidentSlots = 1ull << 22;  // message slots (metadata and digest rings)
+constexpr uint64_t kResidentItems = 1ull << 20;  // work-item ring entries (a power of two)
+constexpr uint64_t kResidentIdleTicks = 500000;  // a launch ends 5 ms (100 MHz ticks) after its last item
+constexpr uint64_t kResidentMaxTicks = 1000000000;  // and after 10 s in any case (the loop relaunches)
 
 enum class St { Pending, Admitted, Launched, Done };
 
@@ -96,6 +102,11 @@ struct Req {
     std::shared_ptr<CopyMark> copied;  // its staging group's copies
     bool stalled = false;           // was held back at the head of the queue
     int cls = 0;                    // 0: short chains only, 1: has a long chain
+    // resident mode
+    uint64_t slot0 = Arena::kFail;  // first of its n message slots
+    std::vector<ServeItem> items;   // its work items (built by the staging thread)
+    uint64_t item0 = 0;             // ring position of its first published item
+    uint64_t checked = 0;           // items seen done so far
 };
 
 struct Step {
@@ -186,6 +197,27 @@ struct hb_server {
     uint8_t *d_meta[kStreams] = {};
     std::unique_ptr<Step> busy[kStreams];
     int n_streams = kStreams;       // compute streams in use
+    // resident mode: one launch of the serving kernel takes published work items; the rings
+    // are pinned, coherent host memory the kernel reaches through its device mapping
+    bool resident = false;
+    ServeItem *r_items = nullptr;   // item ring (kResidentItems)
+    uint64_t *r_ctl = nullptr;      // [0] items published (tail), [1] stop flag (low word)
+    uint32_t *r_done = nullptr;     // per item ring entry: its position + 1 once hashed
+    uint64_t *r_off = nullptr, *r_len = nullptr;  // per message slot
+    uint32_t *r_slot = nullptr;     // per message slot: the caller's message index + slot0
+    uint8_t *r_dig = nullptr;       // digest ring, 32 bytes per slot
+    uint8_t *r_dev = nullptr;       // device: item ring copy, head, tail, stop
+    ServeRings rings{};
+    Arena slots;                    // message slots (owned by the loop thread)
+    uint64_t published = 0;         // items published
+    uint32_t gen = 0;               // launches so far
+    hipStream_t r_stream = nullptr;
+    hipEvent_t r_ev = nullptr;      // recorded after each launch
+    bool r_launched = false;
+    int r_wgs = 0;                  // workgroups per launch
+    std::vector<Req *> r_inflight;  // published, not finished
+    int r_fail = HB_OK;             // set once a launch fails: every later request fails too
+    std::string r_fail_why;
     std::chrono::steady_clock::time_point t0;
     // stats
     std::atomic<uint64_t> completed{0}, steps{0}, stalls{0}, peak{0};
@@ -281,6 +313,41 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
     return HB_OK;
 }
 
+// Resident mode, on a staging thread: fill the request's message slots and build its work
+// items.  Its messages are ordered by algorithm and, within one, by block count in
+// power-of-two classes, longest first, so the lanes of an item finish close together; slot
+// k holds the message's arena offset, length and the digest slot of its original index.
+void prepare_items(hb_server *s, Req *r)
+{
+    constexpr int kClasses = 64;
+    std::vector<uint32_t> count(3 * kClasses, 0);
+    auto cls = [](uint64_t len) {
+        uint64_t nb = (len + 8) / 64 + 1;
+        int c = 0;
+        while (nb > 1) { nb >>= 1; ++c; }
+        return kClasses - 1 - c;  // longest first
+    };
+    auto algo_of = [&](uint64_t i) { return r->algo < 0 ? int(r->algos[i]) : r->algo; };
+    for (uint64_t i = 0; i < r->n; ++i) count[algo_of(i) * kClasses + cls(r->lens[i])]++;
+    std::vector<uint32_t> start(3 * kClasses + 1, 0);
+    for (int k = 0; k < 3 * kClasses; ++k) start[k + 1] = start[k] + count[k];
+    std::vector<uint32_t> next(start.begin(), start.end() - 1);
+    uint64_t pos = r->arena_off;
+    for (uint64_t i = 0; i < r->n; ++i) {
+        const uint64_t k = r->slot0 + next[algo_of(i) * kClasses + cls(r->lens[i])]++;
+        s->r_off[k] = pos;
+        s->r_len[k] = r->lens[i];
+        s->r_slot[k] = uint32_t(r->slot0 + i);
+        pos += r->lens[i];
+    }
+    r->items.clear();
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t b = start[a * kClasses], e = start[(a + 1) * kClasses];
+        for (uint32_t f = b; f < e; f += 64)
+            r->items.push_back(ServeItem{uint32_t(r->slot0) + f, std::min<uint32_t>(64, e - f), uint32_t(a), 0});
+    }
+}
+
 // Staging thread: take admitted requests in order -- the head of the queue and the
 // requests after it whose arena ranges continue it (up to the allocator's alignment), up
 // to kPiece bytes -- stage them as one group and hand them to the loop.
@@ -314,6 +381,8 @@ void stager_loop(hb_server *s, int w)
         }
         const int rc = stage_group(s, g, grp.data(), int(grp.size()));
         const std::string why = rc != HB_OK ? last_error_text() : std::string();
+        if (rc == HB_OK && s->resident)
+            for (Req *r : grp) prepare_items(s, r);
         {
             std::lock_guard<std::mutex> lk(s->mu);
             const double t1 = s->now();
@@ -468,6 +537,157 @@ void finish_step(hb_server *s, int k, int status, const std::string &why)
     s->cv_done.notify_all();
 }
 
+// Resident mode: publish the work items of staged requests whose payload has landed (their
+// copy mark seen complete), in staging order, while the item ring has room.
+int resident_publish(hb_server *s)
+{
+    std::vector<Req *> ready;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (int c = 0; c < 2; ++c) {
+            std::vector<Req *> &q = s->staged[c];
+            size_t keep = 0;
+            for (size_t i = 0; i < q.size(); ++i) {
+                Req *r = q[i];
+                const bool landed = !r->copied || r->copied->t >= 0 || r->res.status != HB_OK;
+                if (landed) {
+                    r->st = St::Launched;
+                    ready.push_back(r);
+                } else {
+                    q[keep++] = r;
+                }
+            }
+            q.resize(keep);
+        }
+    }
+    if (ready.empty()) return 0;
+    const uint64_t mask = kResidentItems - 1;
+    uint64_t oldest = s->published;
+    for (Req *r : s->r_inflight) oldest = std::min(oldest, r->item0 + r->checked);
+    const double t = s->now();
+    std::vector<Req *> failed;
+    for (Req *r : ready) {
+        if (r->res.status != HB_OK) {  // staging failed: nothing to hash
+            failed.push_back(r);
+            continue;
+        }
+        // the ring never holds more than kResidentItems unfinished items (it has far more
+        // room than max_slots requests of 2^20 messages need: 16,384 items each at most)
+        while (s->published + r->items.size() - oldest > kResidentItems) {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            oldest = s->published;
+            for (Req *q : s->r_inflight) {
+                while (q->checked < q->items.size()) {
+                    const uint64_t h = q->item0 + q->checked;
+                    if (__atomic_load_n(&s->r_done[h & mask], __ATOMIC_ACQUIRE) != uint32_t(h + 1)) break;
+                    q->checked++;
+                }
+                oldest = std::min(oldest, q->item0 + q->checked);
+            }
+        }
+        r->item0 = s->published;
+        r->checked = 0;
+        for (size_t k = 0; k < r->items.size(); ++k) s->r_items[(s->published + k) & mask] = r->items[k];
+        s->published += r->items.size();
+        s->r_inflight.push_back(r);
+    }
+    __atomic_store_n(&s->r_ctl[0], s->published, __ATOMIC_RELEASE);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (Req *r : ready) {
+            r->t_launch = t;
+            r->t_exec0 = t;
+        }
+    }
+    for (Req *r : failed) {  // no items: finishes at once with its staging failure
+        if (r->payload) s->arena.release(r->arena_off, r->payload);
+        s->slots.release(r->slot0, r->n);
+        std::lock_guard<std::mutex> g(s->mu);
+        r->t_h2d = r->t_exec1 = r->t_done = t;
+        r->st = St::Done;
+        s->slots_used--;
+    }
+    if (!failed.empty()) s->cv_done.notify_all();
+    return int(ready.size());
+}
+
+// Resident mode: finish the published requests whose items are all done (their digests
+// to the callers' buffers, memory and slots released), fail them all if the launch failed,
+// and relaunch the serving kernel when items wait and no launch is running.  Returns the
+// number of requests finished.
+int resident_progress(hb_server *s)
+{
+    const uint64_t mask = kResidentItems - 1;
+    bool running = false;
+    if (s->r_launched) {
+        const hipError_t q = hipEventQuery(s->r_ev);
+        if (q == hipErrorNotReady) running = true;
+        else if (q != hipSuccess && s->r_fail == HB_OK) {
+            s->r_fail = HB_EHIP;
+            s->r_fail_why = std::string("hb_server: serving kernel failed on the device: ") + hipGetErrorString(q);
+        }
+        if (!running) s->r_launched = false;
+    }
+    const int fail = s->r_fail;
+    const std::string why = s->r_fail_why;
+    poll_marks(s);
+    const double t = s->now();
+    int finished = 0;
+    size_t keep = 0;
+    for (size_t i = 0; i < s->r_inflight.size(); ++i) {
+        Req *r = s->r_inflight[i];
+        while (fail == HB_OK && r->checked < r->items.size()) {
+            const uint64_t h = r->item0 + r->checked;
+            if (__atomic_load_n(&s->r_done[h & mask], __ATOMIC_ACQUIRE) != uint32_t(h + 1)) break;
+            r->checked++;
+        }
+        if (fail == HB_OK && r->checked < r->items.size()) {
+            s->r_inflight[keep++] = r;
+            continue;
+        }
+        const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
+        if (fail == HB_OK) {
+            // slot k holds the digest of message r_slot[k] - slot0 (slots are in item order)
+            for (uint64_t k = r->slot0; k < r->slot0 + r->n; ++k)
+                std::memcpy(r->out + (s->r_slot[k] - r->slot0) * ds, s->r_dig + k * 32, ds);
+        }
+        const double h2d = r->copied ? (r->copied->t >= 0 ? std::min(r->copied->t, r->t_exec0) : r->t_exec0) : -1;
+        r->copied.reset();
+        if (r->payload) s->arena.release(r->arena_off, r->payload);
+        s->slots.release(r->slot0, r->n);
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            r->res.fail(fail, why);
+            r->t_h2d = h2d >= 0 ? h2d : r->t_staged;
+            r->t_exec1 = t;
+            r->t_done = t;
+            r->st = St::Done;
+            s->slots_used--;
+        }
+        ++finished;
+    }
+    s->r_inflight.resize(keep);
+    if (finished) {
+        s->completed += uint64_t(finished);
+        s->cv_done.notify_all();
+    }
+    if (!s->r_inflight.empty() && !running && s->r_fail == HB_OK) {
+        // items wait and no launch takes them: start one (head and tail persist on the
+        // device, so it picks up whatever the last launch left)
+        const hipError_t e = launch_serve(s->rings, ++s->gen, s->r_wgs, s->r_stream);
+        const hipError_t er = e == hipSuccess ? hipEventRecord(s->r_ev, s->r_stream) : e;
+        if (er != hipSuccess) {
+            s->fatal = HB_EHIP;
+            s->r_fail = HB_EHIP;
+            s->r_fail_why = std::string("hb_server: serving kernel launch: ") + hipGetErrorString(er);
+        } else {
+            s->r_launched = true;
+            s->steps++;
+        }
+    }
+    return finished;
+}
+
 void loop(hb_server *s)
 {
     hipSetDevice(s->device);
@@ -478,7 +698,7 @@ void loop(hb_server *s)
         std::fill(launch_cls, launch_cls + kStreams, -1);
         {
             std::unique_lock<std::mutex> g(s->mu);
-            bool any_busy = false;
+            bool any_busy = !s->r_inflight.empty();
             for (auto &b : s->busy) any_busy |= bool(b);
             if (s->pending.empty() && s->to_stage.empty() && s->staging_inflight == 0 && s->staged[0].empty() &&
                 s->staged[1].empty() && !any_busy) {
@@ -486,11 +706,20 @@ void loop(hb_server *s)
                 s->cv_work.wait_for(g, std::chrono::milliseconds(50));
                 continue;
             }
-            admitted = admit_in_order(s->pending, s->arena, s->slots_used, s->max_slots, [&](Req *r) {
-                r->st = St::Admitted;
-                r->t_admit = s->now();
-                s->to_stage.push_back(r);
-            });
+            admitted = admit_in_order(
+                s->pending, s->arena, s->slots_used, s->max_slots,
+                [&](Req *r) {
+                    r->st = St::Admitted;
+                    r->t_admit = s->now();
+                    s->to_stage.push_back(r);
+                },
+                [&](Req *r) {  // resident mode: message slots too
+                    if (!s->resident) return true;
+                    const uint64_t o = s->slots.alloc(r->n);
+                    if (o == Arena::kFail) return false;
+                    r->slot0 = o;
+                    return true;
+                });
             if (!s->pending.empty() && !s->pending.front()->stalled) {
                 s->pending.front()->stalled = true;
                 s->stalls++;
@@ -511,9 +740,17 @@ void loop(hb_server *s)
             in.now = s->now();
             in.min_batch = kMinBatch;
             in.max_wait = kMaxWait;
-            choose_launches(in, launch_cls);
+            if (!s->resident) choose_launches(in, launch_cls);
         }
         if (admitted) s->cv_stage.notify_all();
+        if (s->resident) {
+            // resident mode: requests join the running launch as soon as their payload lands
+            poll_marks(s);
+            const int published = resident_publish(s);
+            const int finished = resident_progress(s);
+            if (!published && !finished && !admitted) std::this_thread::sleep_for(std::chrono::microseconds(10));
+            continue;
+        }
         // 2. launch steps on idle compute streams
         for (int k = 0; k < s->n_streams; ++k) {
             if (launch_cls[k] < 0) continue;
@@ -612,6 +849,68 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
     // schedule words beside the bulk -- the chain is what such a step's latency is.
     // HB_SERVER_LONG_PLAN_FLAGS sets the long-chain plans' flags, HB_SERVER_PLAN_FLAGS
     // every plan's.  Plans launch eagerly.
+    if (const char *v = std::getenv("HB_SERVER_MODE")) s->resident = std::strcmp(v, "resident") == 0;
+    if (s->resident) {
+        // resident mode: the rings (pinned, coherent, mapped), the device copy of the item
+        // ring with its head, tail and stop words, one stream for the serving launches
+        const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+        auto pinned = [&](void **p, uint64_t bytes) { return hipHostMalloc(p, bytes, fl); };
+        if ((e = pinned(reinterpret_cast<void **>(&s->r_items), kResidentItems * sizeof(ServeItem))) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_ctl), 256)) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_done), kResidentItems * 4)) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_off), kResidentSlots * 8)) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_len), kResidentSlots * 8)) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_slot), kResidentSlots * 4)) != hipSuccess ||
+            (e = pinned(reinterpret_cast<void **>(&s->r_dig), kResidentSlots * 32)) != hipSuccess)
+            return fail(HB_ENOMEM, "hb_server_create: pinned serving rings", hipSuccess);
+        std::memset(s->r_ctl, 0, 256);
+        std::memset(s->r_done, 0, kResidentItems * 4);
+        const uint64_t dev_bytes = kResidentItems * sizeof(ServeItem) + 256;
+        if ((e = hipMalloc(reinterpret_cast<void **>(&s->r_dev), dev_bytes)) != hipSuccess)
+            return fail(HB_ENOMEM, "hb_server_create: device item ring", hipSuccess);
+        if ((e = hipMemset(s->r_dev + kResidentItems * sizeof(ServeItem), 0, 256)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: device ring words", e);
+        ServeRings &R = s->rings;
+        void *m = nullptr;
+        auto map = [&](void *h) {
+            return hipHostGetDevicePointer(&m, h, 0) == hipSuccess ? m : nullptr;
+        };
+        R.h_items = static_cast<const ServeItem *>(map(s->r_items));
+        R.h_tail = static_cast<const uint64_t *>(map(s->r_ctl));
+        R.h_stop = reinterpret_cast<const uint32_t *>(R.h_tail ? R.h_tail + 1 : nullptr);
+        R.done = static_cast<uint32_t *>(map(s->r_done));
+        R.off = static_cast<const uint64_t *>(map(s->r_off));
+        R.len = static_cast<const uint64_t *>(map(s->r_len));
+        R.digests = static_cast<uint8_t *>(map(s->r_dig));
+        if (!R.h_items || !R.h_tail || !R.done || !R.off || !R.len || !R.digests)
+            return fail(HB_EHIP, "hb_server_create: device mapping of serving rings", hipErrorInvalidValue);
+        R.arena = s->d_arena;
+        R.d_items = reinterpret_cast<ServeItem *>(s->r_dev);
+        uint64_t *words = reinterpret_cast<uint64_t *>(s->r_dev + kResidentItems * sizeof(ServeItem));
+        R.d_head = words;
+        R.d_tail = words + 1;
+        R.d_stop = reinterpret_cast<uint32_t *>(words + 2);
+        R.items_cap = kResidentItems;
+        R.idle_ticks = kResidentIdleTicks;
+        if (const char *v = std::getenv("HB_SERVER_RESIDENT_IDLE_MS"))  // 100 MHz ticks per ms
+            R.idle_ticks = uint64_t(std::max(1, std::min(60000, std::atoi(v)))) * 100000ull;
+        R.max_ticks = kResidentMaxTicks;
+        s->slots.reset(kResidentSlots);
+        int cus = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: CU count", e);
+        s->r_wgs = std::max(cus, 1);  // one workgroup (four waves) per CU
+        if (const char *v = std::getenv("HB_SERVER_RESIDENT_WGS")) s->r_wgs = std::max(1, std::min(65536, std::atoi(v)));
+        if ((e = hipStreamCreateWithFlags(&s->r_stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s->r_ev, hipEventDisableTiming)) != hipSuccess)
+            return fail(HB_EHIP, "hb_server_create: serving stream", e);
+        s->n_streams = 0;
+        hb_server *p = s.release();
+        for (int w = 0; w < p->n_stagers; ++w) p->stager[w].thr = std::thread(stager_loop, p, w);
+        p->thr = std::thread(loop, p);
+        *out = p;
+        return HB_OK;
+    }
     int n_long = kLongStreamsDefault;
     // a process started with GPU_MAX_HW_QUEUES >= 8 (HIP's hardware queues per process)
     // has queues for a second long-chain stream
@@ -802,6 +1101,11 @@ void hb_server_destroy(hb_server *s)
     }
     s->cv_work.notify_all();
     if (s->thr.joinable()) s->thr.join();
+    // resident mode: the host's stop flag ends the serving kernel's wait for items at once
+    // (it would otherwise stay up to its idle limit); it must be gone before any free below,
+    // since freeing memory waits for the device's work to finish
+    if (s->r_ctl) __atomic_store_n(reinterpret_cast<uint32_t *>(s->r_ctl + 1), 1u, __ATOMIC_RELEASE);
+    if (s->r_stream) hipStreamSynchronize(s->r_stream);
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->stop_stagers = true;
@@ -824,6 +1128,13 @@ void hb_server_destroy(hb_server *s)
         if (s->d_meta[k]) hipFree(s->d_meta[k]);
         if (s->compute[k]) hipStreamDestroy(s->compute[k]);
     }
+    if (s->r_stream) hipStreamDestroy(s->r_stream);  // the launch ended above
+    if (s->r_ev) hipEventDestroy(s->r_ev);
+    for (void *h : {static_cast<void *>(s->r_items), static_cast<void *>(s->r_ctl), static_cast<void *>(s->r_done),
+                    static_cast<void *>(s->r_off), static_cast<void *>(s->r_len), static_cast<void *>(s->r_slot),
+                    static_cast<void *>(s->r_dig)})
+        if (h) hipHostFree(h);
+    if (s->r_dev) hipFree(s->r_dev);
     for (hipStream_t c : s->copy_in) {
         if (!c) continue;
         hipStreamSynchronize(c);

@@ -282,6 +282,18 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, h
     return hipSuccess;
 }
 
+hipError_t hipMemset(void *dst, int value, size_t n)
+{
+    std::memset(dst, value, n);
+    return hipSuccess;
+}
+
+hipError_t hipDeviceGetAttribute(int *value, hipDeviceAttribute_t, int)
+{
+    *value = 8;  // "CUs" of the stand-in device
+    return hipSuccess;
+}
+
 const char *hipGetErrorString(hipError_t e)
 {
     switch (e) {

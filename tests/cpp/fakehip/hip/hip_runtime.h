@@ -20,6 +20,8 @@ typedef enum hipError_t {
 typedef struct FakeStream *hipStream_t;
 typedef struct FakeEvent *hipEvent_t;
 
+typedef enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 63 } hipDeviceAttribute_t;
+
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                      hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
 
@@ -45,4 +47,6 @@ hipError_t hipEventRecord(hipEvent_t event, hipStream_t stream);
 hipError_t hipEventQuery(hipEvent_t event);
 hipError_t hipEventSynchronize(hipEvent_t event);
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind kind, hipStream_t stream);
+hipError_t hipMemset(void *dst, int value, size_t n);
+hipError_t hipDeviceGetAttribute(int *value, hipDeviceAttribute_t attr, int device);
 const char *hipGetErrorString(hipError_t e);

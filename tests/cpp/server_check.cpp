@@ -23,6 +23,7 @@
 
 #include "../../include/hb.h"
 #include "fakehip/fake_hip.hpp"
+#include "../../paper_2407_09333_amd/csrc/hb_serve.hpp"
 
 // ---- stand-ins for the rest of libhb that the serving loop calls -------------------------
 
@@ -46,6 +47,47 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s
 }  // namespace hb
 
 extern "C" const char *hb_last_error(void) { return hb::t_err.c_str(); }
+
+static void fingerprint(int algo, const uint8_t *m, uint64_t len, uint8_t *out, uint32_t stride);
+
+// The resident serving kernel, emulated on the stand-in stream's host thread: copy newly
+// published items from the host ring to the "device" ring, take them in order, write each
+// message's fingerprint to its digest slot and the item's done flag, and leave when the
+// host says stop or 5 ms pass without an item -- the kernel's protocol, one worker.
+namespace hb {
+hipError_t launch_serve(const ServeRings &R, uint32_t gen, int, hipStream_t stream)
+{
+    return fake_hip_launch(stream, [R, gen] {
+        using clk = std::chrono::steady_clock;
+        const uint64_t mask = R.items_cap - 1;
+        auto last = clk::now();
+        uint64_t dt = __atomic_load_n(R.d_tail, __ATOMIC_ACQUIRE);
+        for (;;) {
+            const uint32_t stop = __atomic_load_n(R.h_stop, __ATOMIC_ACQUIRE);
+            const uint64_t ht = __atomic_load_n(R.h_tail, __ATOMIC_ACQUIRE);
+            if (ht > dt) {
+                for (uint64_t k = dt; k < ht; ++k) R.d_items[k & mask] = R.h_items[k & mask];
+                __atomic_store_n(R.d_tail, ht, __ATOMIC_RELEASE);
+                dt = ht;
+            }
+            uint64_t h = __atomic_load_n(R.d_head, __ATOMIC_ACQUIRE);
+            for (; h < dt; ++h) {
+                const ServeItem it = R.d_items[h & mask];
+                for (uint32_t l = 0; l < it.count; ++l) {
+                    const uint32_t slot = it.first + l;
+                    fingerprint(int(it.algo), R.arena + R.off[slot], R.len[slot], R.digests + uint64_t(slot) * 32, 32);
+                }
+                __atomic_store_n(R.done + (h & mask), uint32_t(h + 1), __ATOMIC_RELEASE);
+                __atomic_store_n(R.d_head, h + 1, __ATOMIC_RELEASE);
+                last = clk::now();
+            }
+            if (stop || clk::now() - last > std::chrono::milliseconds(5)) break;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        __atomic_store_n(R.d_stop, gen, __ATOMIC_RELEASE);
+    });
+}
+}  // namespace hb
 
 // Keyed 64-bit FNV-1a of the message, spread over the digest size: not a hash function of
 // the standards, only a per-message fingerprint that tells slots apart.

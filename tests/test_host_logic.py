@@ -154,14 +154,18 @@ def server_check_exe(tmp_path_factory):
 
 
 @pytest.mark.parametrize("env", [{}, {"GPU_MAX_HW_QUEUES": "8"}, {"HB_SERVER_COPY": "kernel"},
-                                 {"HB_SERVER_STAGERS": "1"}], ids=["default", "8queues", "kernelcopy", "1stager"])
+                                 {"HB_SERVER_STAGERS": "1"}, {"HB_SERVER_MODE": "resident"},
+                                 {"HB_SERVER_MODE": "resident", "GPU_MAX_HW_QUEUES": "8"}],
+                         ids=["default", "8queues", "kernelcopy", "1stager", "resident", "resident8queues"])
 @pytest.mark.parametrize("sanitize", ["thread", "address,undefined"], ids=["tsan", "asan"])
 def test_serving_loop_on_host_stand_in(server_check_exe, sanitize, env):
     """The serving loop itself (csrc/hb_server.cpp, compiled unchanged) on the CPU against a
     host-only stand-in for the HIP runtime (tests/cpp/fakehip: in-order streams on host
     threads, events, stream waits, copies) and for the plan's hashing (a per-message
     fingerprint), under ThreadSanitizer and under AddressSanitizer + UBSan: three client
-    threads submit, cancel and wait on 180 requests against a 2 MiB budget; every request's
+    threads submit, cancel and wait on 180 requests against a 2 MiB budget, with device steps
+    or (resident mode) the resident serving kernel's item protocol emulated on a host
+    thread; every request's
     slots hold its own messages' fingerprints, and no event is destroyed or recorded again
     while in flight, no stream waits on an event never recorded, no destroyed stream or
     event is used, and every event created is destroyed.  Clang's sanitizers are used:
