@@ -267,24 +267,6 @@ def bench_fixed(args):
         del os.environ["HB_PLAIN_LDS"]
     per_algo["md5"]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
     per_algo["md5"]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
-    # what a plain read of the same 1 GiB reaches on this GPU (torch's float32 sum reduction
-    # over the bytes viewed as floats: one read-only pass, the values do not matter): the
-    # practical HBM ceiling MD5 is compared with
-    words = msgs.view(torch.float32)
-    rd_ms = []
-    for k in range(args.warmup + args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        words.sum()
-        e1.record(stream)
-        e1.synchronize()
-        if k >= args.warmup:
-            rd_ms.append(e0.elapsed_time(e1))
-    hbm_read = {"kernel": "torch float32 sum over the same 1 GiB (read-only stream)",
-                "ms": round(float(np.mean(rd_ms)), 4), "ms_min": round(float(np.min(rd_ms)), 4),
-                "TBps": round(payload / (float(np.mean(rd_ms)) / 1e3) / 1e12, 3),
-                "TBps_best": round(payload / (float(np.min(rd_ms)) / 1e3) / 1e12, 3)}
-    per_algo["md5"]["frac_of_measured_read_stream"] = round(float(np.mean(rd_ms)) / kms["md5"], 4)
     dom = max(kms, key=kms.get)
     t_dom = kms[dom] / 1e3
     ops_dom = blocks * OPS_PER_BLOCK[dom]
@@ -305,7 +287,6 @@ def bench_fixed(args):
                                "uniform random bytes); one step = the three plain launches",
                    "messages": n, "msg_len": L, "payload_bytes_per_step": 3 * payload},
         "per_algo": per_algo,
-        "hbm_read_stream": hbm_read,
         "roofline": roofline,
         "device": info,
         "kernel_source": kernel_source_hash(),
