@@ -250,23 +250,25 @@ def bench_fixed(args):
             "alu_frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
             "hbm_frac_payload": round(payload / t / 1e9 / HBM_PEAK_GBS, 4),
         }
-    # MD5 again with its message words staged through LDS (HB_PLAIN_LDS=1, coalesced loads,
-    # the same digests): the variant kept as an option, reported beside the default
+    # each algorithm again with its message words staged through LDS (HB_PLAIN_LDS=1,
+    # coalesced loads, the same digests): the variant kept as an option, reported beside
+    # the default
     os.environ["HB_PLAIN_LDS"] = "1"
     try:
-        lds_ms = []
-        for k in range(args.warmup + args.steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            hb.hash_batch_fixed(0, msgs, n, L, out=outs[0], stream=stream)
-            e1.record(stream)
-            e1.synchronize()
-            if k >= args.warmup:
-                lds_ms.append(e0.elapsed_time(e1))
+        for a in range(3):
+            lds_ms = []
+            for k in range(args.warmup + args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                hb.hash_batch_fixed(a, msgs, n, L, out=outs[a], stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                if k >= args.warmup:
+                    lds_ms.append(e0.elapsed_time(e1))
+            per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
+            per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
     finally:
         del os.environ["HB_PLAIN_LDS"]
-    per_algo["md5"]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
-    per_algo["md5"]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
     dom = max(kms, key=kms.get)
     t_dom = kms[dom] / 1e3
     ops_dom = blocks * OPS_PER_BLOCK[dom]
