@@ -23,6 +23,9 @@ namespace hb {
 
 constexpr int kServeThreads = 256;
 constexpr uint64_t kMaxClaim = 16;  // items one wave claims at once at most
+// s_waitcnt immediate: vmcnt(0), expcnt and lgkmcnt left at their maxima (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr uint64_t kCoopBlocks = 128;     // items whose longest message has this many blocks,
 constexpr uint32_t kCoopMaxMessages = 4;  // and at most this many messages, take the cooperative
                                           // long path: each window then holds >= 16 blocks per
@@ -144,7 +147,14 @@ __device__ __forceinline__ void serve_item(const ServeRings &R, const ServeItem 
         const uint32_t *src = wave_lds + c * 4u;
         u32x4 v;
         v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = src[3];
-        *reinterpret_cast<HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(dst + uint64_t(c) * 16u)) = v;
+        // system-coherent 16-byte store (sc0 sc1), written through to pinned host memory
+        // rather than held in the L2: the items' done flags then need these stores complete
+        // (one vmcnt wait), not a write-back of the whole L2 per claim.  The compiler cannot
+        // see this store, so the wait state the ISA asks before a VALU overwrites the data
+        // registers of a store of more than 8 bytes is part of the asm.  (Four dword atomic
+        // stores instead cut the serving rate more than tenfold.)
+        HB_GLOBAL u32x4 *d = reinterpret_cast<HB_GLOBAL u32x4 *>(reinterpret_cast<uintptr_t>(dst + uint64_t(c) * 16u));
+        asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1\n\ts_nop 0" : : "v"(d), "v"(v) : "memory");
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // reads done before the next item's writes
 }
@@ -224,8 +234,11 @@ __global__ __launch_bounds__(kServeThreads) void k_serve(ServeRings R, uint32_t 
                 const ServeItem it = R.d_items[(h + k) & mask];
                 serve_item(R, it, lane, digest_lds[threadIdx.x / 64u], sched_lds[threadIdx.x / 64u]);
             }
-            // digests visible to the host before the items' done flags
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            // digests visible to the host before the items' done flags: they were stored
+            // write-through (serve_item), so it is enough that every store has completed
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             if (lane < take)
                 __hip_atomic_store(R.done + ((h + lane) & mask), uint32_t(h + lane + 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_SYSTEM);
