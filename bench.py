@@ -739,10 +739,11 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
     """Open-loop Poisson arrivals; each request 1..10,000 messages (log-uniform count),
     algorithm uniform over the three, lengths log-normal (median 256 B, cap 64 KiB); device
     budget 64 GiB.  A saturating burst of 8,192 requests gives a first estimate C_burst
-    (adjacent requests then share transfers, so it overstates what Poisson arrivals get);
+    (adjacent requests then share transfers, so it can miss what Poisson arrivals get);
     the capacity C is then the highest offered rate, found by bisection over short
-    open-loop trials between 0.25 and 1.1 C_burst, at which the achieved rate tracks the
-    offered one (>= 97 %) with p99 <= 10 ms.  The headline is p50 / p99 at 0.7 C; the sweep
+    open-loop trials (from 0.25 C_burst; the bracket's upper end starts at 1.1 C_burst and
+    is raised while still sustained), at which the achieved rate tracks the offered one
+    (>= 97 %) with p99 <= 10 ms.  The headline is p50 / p99 at 0.7 C; the sweep
     adds 0.5 and 0.9 C and the fixed rate of 8,000 req/s."""
     from paper_2407_09333_amd import hb, workloads
 
@@ -764,22 +765,32 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
     burst_rps = len(burst) / (t1 - t0)
     mean_bytes = float(np.mean([int(r.lengths.sum()) for r in pool]))
     print(f"bench: serving burst capacity {burst_rps:.0f} req/s", file=sys.stderr, flush=True)
-    # bisection for the open-loop capacity
-    lo, hi = 0.25 * burst_rps, 1.1 * burst_rps
+    # open-loop capacity: bracket it (from 0.25 C_burst up, the upper end raised by 1.5x
+    # while it is still sustained, at most three times), then bisect
     trials = []
-    run = _serve_open_loop(srv, pool, lo, int(max(lo * trial_s, 300)), seed=201)
-    trials.append(run)
-    if not _sustained(run):
-        hi = lo
+
+    def trial(rate, seed):
+        run = _serve_open_loop(srv, pool, rate, int(max(rate * trial_s, 300)), seed=seed)
+        trials.append(run)
+        print(f"bench: serving trial {rate:.0f} req/s: achieved {run['achieved_req_per_s']:.0f}, "
+              f"p99 {run['p99_ms']} ms", file=sys.stderr, flush=True)
+        return _sustained(run)
+
+    lo = 0.25 * burst_rps
+    hi = lo
+    if trial(lo, 201):
+        hi = 1.1 * burst_rps
+        for grow in range(3):
+            if not trial(hi, 210 + grow):
+                break
+            lo, hi = hi, 1.5 * hi
+        else:
+            hi = lo  # still sustained at the last bracket: C is at least lo
     for it in range(5):
         if hi <= lo * 1.03:
             break
         mid = 0.5 * (lo + hi)
-        run = _serve_open_loop(srv, pool, mid, int(max(mid * trial_s, 300)), seed=202 + it)
-        trials.append(run)
-        print(f"bench: serving trial {mid:.0f} req/s: achieved {run['achieved_req_per_s']:.0f}, "
-              f"p99 {run['p99_ms']} ms", file=sys.stderr, flush=True)
-        if _sustained(run):
+        if trial(mid, 202 + it):
             lo = mid
         else:
             hi = mid

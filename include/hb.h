@@ -319,7 +319,8 @@ typedef struct hb_server hb_server;
  * waves claim them (several at once when a backlog has built up), hash them and write the
  * digests and a done flag straight to pinned host memory.  The kernel leaves after 5 ms
  * without items (HB_SERVER_RESIDENT_IDLE_MS) or when the server is destroyed, and the loop
- * starts it again when items wait; one workgroup per CU (HB_SERVER_RESIDENT_WGS).  While it
+ * starts it again when items wait; one workgroup per two CUs (HB_SERVER_RESIDENT_WGS sets the
+ * count: with one on every CU the payload copies, kernels themselves, lag at high load).  While it
  * runs, device-wide synchronisations of the process (hipDeviceSynchronize, hipFree) wait
  * for it.  Returns HB_EINVAL for a null server pointer,
  * a budget below 256 bytes or max_slots <= 0, HB_ENOMEM if the device arena or pinned

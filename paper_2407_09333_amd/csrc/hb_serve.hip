@@ -21,15 +21,10 @@
 
 namespace hb {
 
-constexpr int kServeThreads = 256;
 constexpr uint64_t kMaxClaim = 16;  // items one wave claims at once at most
 // s_waitcnt immediate: vmcnt(0), expcnt and lgkmcnt left at their maxima (gfx9 encoding:
 // vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 constexpr int kWaitVmcnt0 = 0x0F70;
-constexpr uint64_t kCoopBlocks = 128;     // items whose longest message has this many blocks,
-constexpr uint32_t kCoopMaxMessages = 4;  // and at most this many messages, take the cooperative
-                                          // long path: each window then holds >= 16 blocks per
-                                          // chain, so its load latency is amortised
 
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }  // 100 MHz
 
@@ -127,11 +122,8 @@ __device__ __forceinline__ void serve_long_item(const ServeRings &R, const Serve
 __device__ __forceinline__ void serve_item(const ServeRings &R, const ServeItem &it, uint32_t lane, uint32_t *wave_lds,
                                            u32x4 (*sched)[64])
 {
-    // the item's longest message (its messages share a block-count class, so the first
-    // lane's is representative; the long path handles any mix within the item)
-    const uint64_t nb0 = block_count(R.len[it.first]);
     uint32_t *mine = wave_lds + lane * 8u;
-    if (nb0 >= kCoopBlocks && it.count <= kCoopMaxMessages) {
+    if (it.blocks >= kServeCoopBlocks && it.count <= kServeCoopMaxMessages) {
         if (it.algo == MD5) serve_long_item<MD5>(R, it, lane, sched, mine);
         else if (it.algo == SHA1) serve_long_item<SHA1>(R, it, lane, sched, mine);
         else serve_long_item<SM3>(R, it, lane, sched, mine);
@@ -220,7 +212,23 @@ __global__ __launch_bounds__(kServeThreads) void k_serve(ServeRings R, uint32_t 
             // and release below are cache-wide operations of the XCD's L2, and under load
             // they, not the hashing, bound the items per second
             const uint64_t backlog = t - h;
-            const uint64_t take = backlog >= 32u * kMaxClaim ? kMaxClaim : (backlog >= 64u ? backlog / 32u : 1u);
+            uint64_t take = backlog >= 32u * kMaxClaim ? kMaxClaim : (backlog >= 64u ? backlog / 32u : 1u);
+            if (take > 1) {
+                // only as many items as fit kServeClaimBlocks (the first always): their
+                // `blocks`, read before the claim's acquire, are a hint -- a stale value
+                // changes how many items this wave takes, never what it computes
+                uint32_t w = 0;
+                if (lane < take)
+                    w = min(__hip_atomic_load(&R.d_items[(h + lane) & mask].blocks, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT),
+                            1u << 20);
+                for (int d = 1; d < 64; d <<= 1) {  // inclusive prefix sum over the lanes
+                    const uint32_t o = __shfl_up(w, d);
+                    if (lane >= uint32_t(d)) w += o;
+                }
+                const uint64_t over = __ballot(lane > 0 && lane < take && w > kServeClaimBlocks);
+                if (over) take = uint64_t(__builtin_ctzll(over));
+            }
             uint32_t won = 0;
             if (lane == 0)
                 won = __hip_atomic_compare_exchange_strong(R.d_head, &h, h + take, __ATOMIC_RELAXED, __ATOMIC_RELAXED,

@@ -210,6 +210,10 @@ struct hb_server {
     ServeRings rings{};
     Arena slots;                    // message slots (owned by the loop thread)
     uint64_t published = 0;         // items published
+    // items published and not yet seen done (written by the loop, read by the staging
+    // threads to choose how to form a request's items)
+    std::atomic<uint64_t> r_outstanding{0};
+    uint64_t r_latency_items = 0;   // below this many outstanding items: latency formation
     uint32_t gen = 0;               // launches so far
     hipStream_t r_stream = nullptr;
     hipEvent_t r_ev = nullptr;      // recorded after each launch
@@ -340,11 +344,41 @@ void prepare_items(hb_server *s, Req *r)
         s->r_slot[k] = uint32_t(r->slot0 + i);
         pos += r->lens[i];
     }
+    // Items: each algorithm's messages, longest class first, 64 to an item (one per lane).
+    // A request is done when its longest chain is, and a chain's blocks are sequential, so
+    // while the device has idle waves (few items outstanding) each algorithm's longest
+    // messages -- its two longest block-count classes, where they have >= kServeCoopBlocks
+    // blocks -- go into items of at most kServeCoopMaxMessages messages, which the kernel
+    // hashes with the whole wave on each chain's critical path.  Under a backlog that
+    // formation would cost more wave time than it saves latency, so then all items are full.
+    const bool latency = s->r_outstanding.load(std::memory_order_relaxed) < s->r_latency_items;
+    auto item = [&](uint32_t f, uint32_t n, int a) {  // slots slot0 + f .. + n - 1
+        uint64_t nb = 0;
+        for (uint64_t k = r->slot0 + f; k < r->slot0 + f + n; ++k) nb = std::max(nb, (s->r_len[k] + 8) / 64 + 1);
+        r->items.push_back(ServeItem{uint32_t(r->slot0) + f, n, uint32_t(a), uint32_t(std::min<uint64_t>(nb, UINT32_MAX))});
+    };
     r->items.clear();
     for (int a = 0; a < 3; ++a) {
         const uint32_t b = start[a * kClasses], e = start[(a + 1) * kClasses];
-        for (uint32_t f = b; f < e; f += 64)
-            r->items.push_back(ServeItem{uint32_t(r->slot0) + f, std::min<uint32_t>(64, e - f), uint32_t(a), 0});
+        uint32_t f = b;
+        if (latency) {
+            int c0 = 0;
+            while (c0 < kClasses && count[a * kClasses + c0] == 0) ++c0;
+            uint32_t top = b;  // end of the messages taken cooperatively
+            for (int c = c0; c < c0 + 2 && c < kClasses; ++c)
+                if ((uint64_t(1) << (kClasses - 1 - c)) >= kServeCoopBlocks) top = start[a * kClasses + c + 1];
+            const uint32_t n_top = top - b;
+            if (n_top > 0) {
+                const uint32_t k = (n_top + kServeCoopMaxMessages - 1) / kServeCoopMaxMessages;  // items
+                for (uint32_t q = 0; q < k; ++q) {  // sizes differing by at most one
+                    const uint32_t lo = b + uint32_t(uint64_t(n_top) * q / k), hi = b + uint32_t(uint64_t(n_top) * (q + 1) / k);
+                    item(lo, hi - lo, a);
+                }
+                f = top;
+            }
+        }
+        for (; f < e; f += 64)
+            item(f, std::min<uint32_t>(64, e - f), a);
     }
 }
 
@@ -581,6 +615,7 @@ int resident_publish(hb_server *s)
                     const uint64_t h = q->item0 + q->checked;
                     if (__atomic_load_n(&s->r_done[h & mask], __ATOMIC_ACQUIRE) != uint32_t(h + 1)) break;
                     q->checked++;
+                    s->r_outstanding.fetch_sub(1, std::memory_order_relaxed);
                 }
                 oldest = std::min(oldest, q->item0 + q->checked);
             }
@@ -589,6 +624,7 @@ int resident_publish(hb_server *s)
         r->checked = 0;
         for (size_t k = 0; k < r->items.size(); ++k) s->r_items[(s->published + k) & mask] = r->items[k];
         s->published += r->items.size();
+        s->r_outstanding.fetch_add(r->items.size(), std::memory_order_relaxed);
         s->r_inflight.push_back(r);
     }
     __atomic_store_n(&s->r_ctl[0], s->published, __ATOMIC_RELEASE);
@@ -636,15 +672,18 @@ int resident_progress(hb_server *s)
     size_t keep = 0;
     for (size_t i = 0; i < s->r_inflight.size(); ++i) {
         Req *r = s->r_inflight[i];
+        const uint64_t checked0 = r->checked;
         while (fail == HB_OK && r->checked < r->items.size()) {
             const uint64_t h = r->item0 + r->checked;
             if (__atomic_load_n(&s->r_done[h & mask], __ATOMIC_ACQUIRE) != uint32_t(h + 1)) break;
             r->checked++;
         }
         if (fail == HB_OK && r->checked < r->items.size()) {
+            s->r_outstanding.fetch_sub(r->checked - checked0, std::memory_order_relaxed);
             s->r_inflight[keep++] = r;
             continue;
         }
+        s->r_outstanding.fetch_sub(r->items.size() - checked0, std::memory_order_relaxed);  // the rest, on failure too
         const uint64_t ds = r->algo < 0 ? 32 : uint64_t(digest_size(r->algo));
         if (fail == HB_OK) {
             // slot k holds the digest of message r_slot[k] - slot0 (slots are in item order)
@@ -899,8 +938,15 @@ int hb_server_create(hb_server **out, int device, uint64_t hbm_budget_bytes, int
         int cus = 0;
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: CU count", e);
-        s->r_wgs = std::max(cus, 1);  // one workgroup (four waves) per CU
+        // one workgroup (four waves) on every other CU: the payload copies run as kernels
+        // on the copy streams, and with a serving workgroup on every CU their completion
+        // trailed by milliseconds at high load (copy p99 4.5-16.6 ms from 0.5 to 0.9 of
+        // capacity, against 0.2-1.2 ms, and a higher capacity, with half the CUs)
+        s->r_wgs = std::max(cus / 2, 1);
         if (const char *v = std::getenv("HB_SERVER_RESIDENT_WGS")) s->r_wgs = std::max(1, std::min(65536, std::atoi(v)));
+        // latency formation while fewer items are outstanding than half the worker waves
+        s->r_latency_items = uint64_t(s->r_wgs) * (kServeThreads / 64) / 2;
+        if (const char *v = std::getenv("HB_SERVER_RESIDENT_LATENCY_ITEMS")) s->r_latency_items = uint64_t(std::max(0, std::atoi(v)));
         if ((e = hipStreamCreateWithFlags(&s->r_stream, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&s->r_ev, hipEventDisableTiming)) != hipSuccess)
             return fail(HB_EHIP, "hb_server_create: serving stream", e);
