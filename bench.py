@@ -857,6 +857,21 @@ def bench_serve_child(args, mode=None, overload=True):
     return out
 
 
+def _serve_summary(modes):
+    """Both serving modes side by side: open-loop capacity, p50 / p99 at 0.7 C and at the
+    fixed offered rate."""
+    out = {}
+    for name, sv in modes.items():
+        if not sv:
+            continue
+        fixed = next((e for e in sv["sweep"] if e.get("load_fraction") is None), None)
+        out[name] = {"capacity_req_per_s": sv["capacity_req_per_s"],
+                     "p50_p99_ms_at_0.7C": [sv["p50_ms"], sv["p99_ms"]],
+                     "p50_p99_ms_at_fixed_rate": [fixed["p50_ms"], fixed["p99_ms"]] if fixed else None,
+                     "fixed_rate_req_per_s": SERVE_FIXED_RATE}
+    return out
+
+
 def bench_serve_overload(pool, n_req=160_000, budget=64 << 30):
     """Overload burst: about 140 GB of requests (the serving distribution, the pool cycled)
     submitted at once against the 64 GiB device budget, with slots enough that the budget
@@ -922,6 +937,7 @@ def main():
             rec["incremental"] = bench_incremental(args)
             rec["serving"] = serving
             rec["serving_resident"] = serving_resident
+            rec["serving_summary"] = _serve_summary({"steps": serving, "resident": serving_resident})
     elif args.workload == "uneven":
         rec = {"batched_uneven": bench_uneven(args, steps=args.steps, warmup=args.warmup)}
     elif args.workload == "mixed":
