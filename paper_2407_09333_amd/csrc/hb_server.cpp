@@ -33,6 +33,7 @@
 #include "../../include/hb.h"
 #include "hb_arena.hpp"
 #include "hb_internal.hpp"
+#include "hb_items.hpp"
 #include "hb_outcome.hpp"
 #include "hb_policy.hpp"
 #include "hb_serve.hpp"
@@ -318,68 +319,25 @@ int stage_group(hb_server *s, Stager &g, Req *const *rs, int k)
 }
 
 // Resident mode, on a staging thread: fill the request's message slots and build its work
-// items.  Its messages are ordered by algorithm and, within one, by block count in
-// power-of-two classes, longest first, so the lanes of an item finish close together; slot
-// k holds the message's arena offset, length and the digest slot of its original index.
+// items (form_serve_items: slots by algorithm and block-count class, longest first; the
+// latency formation while few items are outstanding).  Slot k holds the message's arena
+// offset, length and the digest slot of its original index.
 void prepare_items(hb_server *s, Req *r)
 {
-    constexpr int kClasses = 64;
-    std::vector<uint32_t> count(3 * kClasses, 0);
-    auto cls = [](uint64_t len) {
-        uint64_t nb = (len + 8) / 64 + 1;
-        int c = 0;
-        while (nb > 1) { nb >>= 1; ++c; }
-        return kClasses - 1 - c;  // longest first
-    };
-    auto algo_of = [&](uint64_t i) { return r->algo < 0 ? int(r->algos[i]) : r->algo; };
-    for (uint64_t i = 0; i < r->n; ++i) count[algo_of(i) * kClasses + cls(r->lens[i])]++;
-    std::vector<uint32_t> start(3 * kClasses + 1, 0);
-    for (int k = 0; k < 3 * kClasses; ++k) start[k + 1] = start[k] + count[k];
-    std::vector<uint32_t> next(start.begin(), start.end() - 1);
+    const bool latency = s->r_outstanding.load(std::memory_order_relaxed) < s->r_latency_items;
+    std::vector<uint32_t> slot_of;
+    form_serve_items(
+        r->n, r->lens, [&](uint64_t i) { return r->algo < 0 ? int(r->algos[i]) : r->algo; }, latency, slot_of,
+        r->items);
     uint64_t pos = r->arena_off;
     for (uint64_t i = 0; i < r->n; ++i) {
-        const uint64_t k = r->slot0 + next[algo_of(i) * kClasses + cls(r->lens[i])]++;
+        const uint64_t k = r->slot0 + slot_of[i];
         s->r_off[k] = pos;
         s->r_len[k] = r->lens[i];
         s->r_slot[k] = uint32_t(r->slot0 + i);
         pos += r->lens[i];
     }
-    // Items: each algorithm's messages, longest class first, 64 to an item (one per lane).
-    // A request is done when its longest chain is, and a chain's blocks are sequential, so
-    // while the device has idle waves (few items outstanding) each algorithm's longest
-    // messages -- its two longest block-count classes, where they have >= kServeCoopBlocks
-    // blocks -- go into items of at most kServeCoopMaxMessages messages, which the kernel
-    // hashes with the whole wave on each chain's critical path.  Under a backlog that
-    // formation would cost more wave time than it saves latency, so then all items are full.
-    const bool latency = s->r_outstanding.load(std::memory_order_relaxed) < s->r_latency_items;
-    auto item = [&](uint32_t f, uint32_t n, int a) {  // slots slot0 + f .. + n - 1
-        uint64_t nb = 0;
-        for (uint64_t k = r->slot0 + f; k < r->slot0 + f + n; ++k) nb = std::max(nb, (s->r_len[k] + 8) / 64 + 1);
-        r->items.push_back(ServeItem{uint32_t(r->slot0) + f, n, uint32_t(a), uint32_t(std::min<uint64_t>(nb, UINT32_MAX))});
-    };
-    r->items.clear();
-    for (int a = 0; a < 3; ++a) {
-        const uint32_t b = start[a * kClasses], e = start[(a + 1) * kClasses];
-        uint32_t f = b;
-        if (latency) {
-            int c0 = 0;
-            while (c0 < kClasses && count[a * kClasses + c0] == 0) ++c0;
-            uint32_t top = b;  // end of the messages taken cooperatively
-            for (int c = c0; c < c0 + 2 && c < kClasses; ++c)
-                if ((uint64_t(1) << (kClasses - 1 - c)) >= kServeCoopBlocks) top = start[a * kClasses + c + 1];
-            const uint32_t n_top = top - b;
-            if (n_top > 0) {
-                const uint32_t k = (n_top + kServeCoopMaxMessages - 1) / kServeCoopMaxMessages;  // items
-                for (uint32_t q = 0; q < k; ++q) {  // sizes differing by at most one
-                    const uint32_t lo = b + uint32_t(uint64_t(n_top) * q / k), hi = b + uint32_t(uint64_t(n_top) * (q + 1) / k);
-                    item(lo, hi - lo, a);
-                }
-                f = top;
-            }
-        }
-        for (; f < e; f += 64)
-            item(f, std::min<uint32_t>(64, e - f), a);
-    }
+    for (ServeItem &it : r->items) it.first += uint32_t(r->slot0);
 }
 
 // Staging thread: take admitted requests in order -- the head of the queue and the

@@ -83,6 +83,27 @@ def test_plan_long_chain_regions(tmp_path, sanitize):
 
 
 @pytest.mark.parametrize("sanitize", [False, True])
+def test_resident_item_formation(tmp_path, sanitize):
+    """The resident serving mode's slot layout and work items (hb_items.hpp) over 3,000
+    random requests (0 to 12,000 messages, log-normal lengths around 256 B, 8 KiB and 40 KB,
+    some up to 16 MiB, one or mixed algorithms), in both formations: slots a permutation
+    ordered by algorithm and block-count class; items covering every slot once with their
+    longest message's block count; the latency formation taking exactly each algorithm's
+    two longest classes of >= 128 blocks into items of at most four, evenly sized."""
+    exe = tmp_path / "items_check"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", str(HERE / "cpp" / "items_check.cpp"), "-o", str(exe)]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and sanitize:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "items ok" in out.stdout
+
+
+@pytest.mark.parametrize("sanitize", [False, True])
 def test_request_failure_text_reaches_the_caller(tmp_path, sanitize):
     """A serving request failed on a staging thread or the loop carries its explanation to
     the thread that waits for it (hb_outcome.hpp, used by hb_server_wait / hb_server_poll):
