@@ -156,12 +156,31 @@ def record_traffic(fetch_dir: str, write_dir: str):
     print(json.dumps(out, indent=1))
 
 
-def cpu_baseline_fixed(msgs_dev, n, L, target_s):
+def cpu_baseline_fixed(msgs_dev, n, L, target_s, gpu_digests=None):
     """The oracle on the first messages of the same buffer: all host cores (the reported
-    value), and one core on a smaller sample, per algorithm."""
+    value), and one core on a smaller sample, per algorithm.  With gpu_digests (algorithm ->
+    (n, digest size) host array of the timed launches' output) every one of those digests is
+    also checked against the oracle's over the whole buffer (untimed; a mismatch raises)."""
     import oracle
 
     cores = len(os.sched_getaffinity(0))
+    verified = None
+    if gpu_digests is not None:
+        whole = msgs_dev[: n * L].cpu().numpy()
+        offs = np.arange(n, dtype=np.uint64) * np.uint64(L)
+        lens = np.full(n, L, np.uint64)
+        t0 = time.perf_counter()
+        for a, got in gpu_digests.items():
+            want = oracle.hash_batch(a, whole, offs, lens, threads=cores)
+            bad = np.flatnonzero((want != got).any(axis=1))
+            if bad.size:
+                raise RuntimeError(f"{ALGO_NAMES[a]}: {bad.size} of {n} digests differ from the oracle "
+                                   f"(first at message {int(bad[0])})")
+        verified = {"messages": n * len(gpu_digests), "all_equal_to_oracle": True,
+                    "what": "every digest of the timed launches (each algorithm, default and LDS-staged "
+                            "kernels) against the oracle over the whole buffer",
+                    "seconds": round(time.perf_counter() - t0, 2)}
+        del whole
     host = msgs_dev[: min(n, 1 << 16) * L].cpu().numpy()
 
     def timed(a, m, threads):
@@ -188,7 +207,7 @@ def cpu_baseline_fixed(msgs_dev, n, L, target_s):
     return {"value": total_bytes / total_t / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": f"first {counts} messages of {L} B of the same buffer, per algorithm, "
                       f"plain C oracle with OpenMP over {cores} threads",
-            "per_algo": per_algo,
+            "per_algo": per_algo, "digests_verified": verified,
             "paper_context": "the paper reports only ratios: its best CPU+GPU split over OpenSSL with OpenMP "
                              "on all CPU threads, SHA-1 55.8x, MD5 1.2x, SM3 22.5x (Sec. V-B, other "
                              "hardware and baseline); per_algo here is the plain C oracle"}
@@ -253,6 +272,7 @@ def bench_fixed(args):
     # each algorithm again with its message words staged through LDS (HB_PLAIN_LDS=1,
     # coalesced loads, the same digests): the variant kept as an option, reported beside
     # the default
+    default_digests = {a: outs[a].clone() for a in range(3)}
     os.environ["HB_PLAIN_LDS"] = "1"
     try:
         for a in range(3):
@@ -267,6 +287,8 @@ def bench_fixed(args):
                     lds_ms.append(e0.elapsed_time(e1))
             per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
             per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
+            if not torch.equal(outs[a], default_digests[a]):
+                raise RuntimeError(f"{ALGO_NAMES[a]}: LDS-staged digests differ from the default kernel's")
     finally:
         del os.environ["HB_PLAIN_LDS"]
     dom = max(kms, key=kms.get)
@@ -294,7 +316,8 @@ def bench_fixed(args):
         "kernel_source": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline_fixed(msgs, n, L, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline_fixed(msgs, n, L, args.cpu_seconds,
+                                                 gpu_digests={a: default_digests[a].cpu().numpy() for a in range(3)})
         for name in ALGO_NAMES:
             rec["per_algo"][name]["over_cpu_oracle_all_cores"] = round(
                 per_algo[name]["hashed_GBps"] / rec["cpu_baseline"]["per_algo"][name]["all_cores_GBps"], 1)
@@ -381,6 +404,7 @@ def bench_uneven(args, steps=5, warmup=2):
     b = workloads.cfg_sm3_uneven(device="cuda")
     offs, lens = hb._dev_i64(b.offsets), hb._dev_i64(b.lengths)
     out = torch.empty((b.n, 32), dtype=torch.uint8, device="cuda")
+    out_d, out_p = torch.empty_like(out), torch.empty_like(out)
     stream = torch.cuda.current_stream()
     plan = hb.Plan(b.n, flags=hb.PLAN_GRAPH | hb.PLAN_AUTOTUNE)
     st_plan = _time_stats(lambda: plan.run(b.messages, offs, lens, algo=2, out=out), steps, warmup, stream)
@@ -388,15 +412,21 @@ def bench_uneven(args, steps=5, warmup=2):
     plan_e = hb.Plan(b.n, flags=0)
     cfg = plan.config()
     plan_e.set_config(cfg["waves_per_cu"], cfg["msgs_per_lane"], cfg["variant"])
-    _time_ms(lambda: plan_e.run(b.messages, offs, lens, algo=2, out=out), steps, 1, stream)
+    _time_ms(lambda: plan_e.run(b.messages, offs, lens, algo=2, out=out_d), steps, 1, stream)
+    same_eager = bool(torch.equal(out_d, out))
     k_ms = plan_e.kernel_ms()
     # the same plan at the untuned defaults (16 waves per CU, one message per lane, default
     # bursts), to state what the autotuner's choice gains
     plan_d = hb.Plan(b.n, flags=hb.PLAN_GRAPH)
-    t_default = _time_ms(lambda: plan_d.run(b.messages, offs, lens, algo=2, out=out), steps, 1, stream)
+    t_default = _time_ms(lambda: plan_d.run(b.messages, offs, lens, algo=2, out=out_d), steps, 1, stream)
+    same_default = bool(torch.equal(out_d, out))
     default_cfg = plan_d.config()
     plan_d.close()
-    t_plain = _time_ms(lambda: hb.hash_batch(2, b.messages, offs, lens, out=out), steps, warmup, stream)
+    t_plain = _time_ms(lambda: hb.hash_batch(2, b.messages, offs, lens, out=out_p), steps, warmup, stream)
+    same_plain = bool(torch.equal(out_p, out))
+    if not (same_eager and same_default and same_plain):
+        raise RuntimeError(f"batched uneven: digests differ (eager plan {same_eager}, untuned plan "
+                           f"{same_default}, plain {same_plain})")
     payload = int(b.lengths.sum())
     blocks = int(((b.lengths.astype(np.int64) + 8) // 64 + 1).sum())
     ops = blocks * OPS_PER_BLOCK["sm3"]
@@ -417,11 +447,12 @@ def bench_uneven(args, steps=5, warmup=2):
                             "four-block bursts), timed on this batch",
         "untuned_config": default_cfg, "untuned_ms": round(t_default, 3),
         "autotune_gain": round(t_default / t_plan, 3),
+        "digests_equal_plain": same_plain,
         "inputs": _inputs_record(args, "sm3_uneven", lengths=b.lengths),
     }
     plan.close()
     plan_e.close()
-    del b, offs, lens, out
+    del b, offs, lens, out, out_d, out_p
     torch.cuda.empty_cache()
     return res
 
@@ -441,7 +472,11 @@ def bench_mixed(args, steps=3, warmup=1):
     plan = hb.Plan(b.n, flags=hb.PLAN_GRAPH)
     st_plan = _time_stats(lambda: plan.run(b.messages, offs, lens, algos=al, out=out), steps, warmup, stream)
     t_plan = st_plan["mean"]
-    t_plain = _time_ms(lambda: hb.hash_batch_mixed(al, b.messages, offs, lens, out=out), steps, warmup, stream)
+    out_p = torch.empty_like(out)
+    t_plain = _time_ms(lambda: hb.hash_batch_mixed(al, b.messages, offs, lens, out=out_p), steps, warmup, stream)
+    same_plain = bool(torch.equal(out_p, out))
+    if not same_plain:
+        raise RuntimeError("batched mixed: the fused plan's digests differ from the plain launches'")
     payload = int(b.lengths.sum())
     nb = (b.lengths.astype(np.int64) + 8) // 64 + 1
     ops = int((nb * np.array([OPS_PER_BLOCK[a] for a in ALGO_NAMES])[b.algos]).sum())
@@ -462,10 +497,11 @@ def bench_mixed(args, steps=3, warmup=1):
         "critical_path_note": "longest chain x ops per block x 4 cycles at 2.1 GHz; the bound uses the "
                               "rounds-only chain (schedule words precomputed off the chain), the other "
                               "figure the full compression",
+        "digests_equal_plain": same_plain,
         "inputs": _inputs_record(args, "mixed_8gib", lengths=b.lengths, algos=b.algos),
     }
     plan.close()
-    del b, offs, lens, al, out
+    del b, offs, lens, al, out, out_p
     torch.cuda.empty_cache()
     return res
 
