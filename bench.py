@@ -78,7 +78,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time in total")
     p.add_argument("--only-headline", action="store_true",
                    help="skip the batched, mixed and serving sections of the default run")
-    p.add_argument("--serve-seconds", type=float, default=15.0)
+    p.add_argument("--serve-seconds", type=float, default=15.0,
+                   help="offered-load time shared by the sweep's other points (0.5 C, 0.9 C, fixed rate)")
+    p.add_argument("--serve-headline-seconds", type=float, default=20.0,
+                   help="offered-load time of the headline point (0.7 C)")
     p.add_argument("--no-overload", action="store_true", help="skip the serving overload burst")
     p.add_argument("--save-inputs", default=None, metavar="DIR",
                    help="also write the seeded length / algorithm arrays of each section as .npy files")
@@ -696,10 +699,12 @@ def bench_digits9(args):
 
 
 # where a serving request's latency goes (from its trace), reported as [p50, p99] ms each:
-# wait for admission, wait for a staging thread, packing + copy enqueue, copy completion,
-# wait for a step launch, wait for the stream / metadata, the step's hashing and digest
-# copy, and host completion (digests to the caller, polling)
-SERVE_PARTS = ("admit_wait", "stager_wait", "pack", "copy", "batch_wait", "exec_wait", "exec", "complete")
+# the client's own lateness (its submit call returning after the scheduled arrival), wait for
+# admission, wait for a staging thread, packing + copy enqueue, copy completion, wait for a
+# step launch, wait for the stream / metadata, the step's hashing and digest copy, and host
+# completion (digests to the caller, polling)
+SERVE_PARTS = ("client_late", "admit_wait", "stager_wait", "pack", "copy", "batch_wait", "exec_wait", "exec",
+               "complete")
 
 
 SERVE_FIXED_RATE = 8000.0  # req/s (about 7 GB/s of payload): the headline offered load
@@ -707,46 +712,71 @@ SERVE_FIXED_RATE = 8000.0  # req/s (about 7 GB/s of payload): the headline offer
 
 def _serve_open_loop(srv, pool, rate, n_req, seed=105):
     """n_req requests (the pool cycled) at Poisson arrivals of the given rate; latency is
-    completion time - scheduled arrival time (no coordinated omission).  Returns the stats
-    of the run and each request's trace split into phases."""
+    completion time - scheduled arrival time (no coordinated omission).  A consumer thread
+    takes each result as it completes (Server.collect: wait, trace into an array, release, in
+    submission order), as a client would, so the run holds only the requests in flight; the
+    interpreter's thread switch interval is cut to 0.1 ms meanwhile so the consumer does not
+    hold up a submission.  Returns the stats of the run and each request's trace split into phases."""
+    import queue
+    import threading
+
     pool_size = len(pool)
+    sizes = [int(r.lengths.sum()) for r in pool]
     arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n_req))
-    tickets, sched = [None] * n_req, np.zeros(n_req)
+    sched = np.zeros(n_req)
+    failure = []
+    q = queue.Queue()
+
+    tr = np.zeros((n_req, len(srv.TRACE_NAMES)))
+
+    def consume():
+        try:
+            for _ in range(n_req):
+                k, t = q.get()
+                srv.collect(t, tr[k])
+        except BaseException as e:  # surfaced by the submitting thread
+            failure.append(e)
+
     s0 = srv.stats()
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
+    consumer = threading.Thread(target=consume, daemon=True)
+    consumer.start()
     start = srv.now() + 0.05
     payload = 0
-    for k in range(n_req):
-        r = pool[k % pool_size]
-        target = start + arrivals[k]
-        while True:
-            d = target - srv.now()
-            if d <= 0:
+    try:
+        for k in range(n_req):
+            r = pool[k % pool_size]
+            target = start + arrivals[k]
+            while True:
+                d = target - srv.now()
+                if d <= 0:
+                    break
+                if d > 0.002:
+                    time.sleep(d - 0.001)
+            sched[k] = target
+            q.put((k, srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)))
+            payload += sizes[k % pool_size]
+            if failure:
                 break
-            if d > 0.002:
-                time.sleep(d - 0.001)
-        sched[k] = target
-        tickets[k] = srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos)
-        payload += int(r.lengths.sum())
-    lat = np.zeros(n_req)
-    phases = np.zeros((n_req, 3))
-    parts = np.zeros((n_req, len(SERVE_PARTS)))
-    done_max = 0.0
-    for k, t in enumerate(tickets):
-        srv.wait(t)
-        tm = srv.trace(t)
-        lat[k] = tm["done"] - sched[k]
-        phases[k] = (tm["admit"] - sched[k], tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"])
-        # a step may be enqueued before its inputs' copy completes (the device then waits
-        # for the copy), so after stage_end the copy and the step launch run side by side:
-        # batch_wait counts only the time after the copy landed until the step was
-        # enqueued, exec_wait from the later of the two until the step began
-        ready = max(tm["launch"], tm["h2d_done"])
-        parts[k] = (tm["admit"] - sched[k], tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
-                    tm["h2d_done"] - tm["stage_end"], ready - tm["h2d_done"],
-                    tm["exec_begin"] - ready, tm["exec_end"] - tm["exec_begin"],
-                    tm["done"] - tm["exec_end"])
-        done_max = max(done_max, tm["done"])
-        srv.release(t)
+        consumer.join()
+    finally:
+        sys.setswitchinterval(switch)
+    if failure:
+        raise failure[0]
+    tm = {name: tr[:, j] for j, name in enumerate(srv.TRACE_NAMES)}
+    lat = tm["done"] - sched
+    phases = np.stack([tm["admit"] - sched, tm["h2d_done"] - tm["admit"], tm["done"] - tm["h2d_done"]], 1)
+    # a step may be enqueued before its inputs' copy completes (the device then waits for the
+    # copy), so after stage_end the copy and the step launch run side by side: batch_wait
+    # counts only the time after the copy landed until the step was enqueued, exec_wait from
+    # the later of the two until the step began
+    ready = np.maximum(tm["launch"], tm["h2d_done"])
+    parts = np.stack([np.maximum(tm["submit"] - sched, 0.0), tm["admit"] - np.maximum(tm["submit"], sched),
+                      tm["stage_begin"] - tm["admit"], tm["stage_end"] - tm["stage_begin"],
+                      tm["h2d_done"] - tm["stage_end"], ready - tm["h2d_done"], tm["exec_begin"] - ready,
+                      tm["exec_end"] - tm["exec_begin"], tm["done"] - tm["exec_end"]], 1)
+    done_max = float(tm["done"].max())
     s1 = srv.stats()
     span = done_max - start
     return {"offered_req_per_s": round(rate, 1), "requests": n_req,
@@ -832,9 +862,13 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
             hi = mid
     cap_rps = lo
     runs = []
+    headline_s = getattr(args, "serve_headline_seconds", 20.0)
     for frac in (0.7,) + tuple(f for f in fractions if f != 0.7) + (None,):
         rate = SERVE_FIXED_RATE if frac is None else frac * cap_rps
-        n_req = int(min(max(rate * seconds / (len(fractions) + 1), 200), 30_000))
+        if frac == 0.7:  # the headline: a long run (hundreds of thousands of requests)
+            n_req = int(min(max(rate * headline_s, 200), 1_000_000))
+        else:
+            n_req = int(min(max(rate * seconds / (len(fractions) + 1), 200), 30_000))
         run = _serve_open_loop(srv, pool, rate, n_req)
         run["load_fraction"] = frac
         runs.append(run)
@@ -856,8 +890,9 @@ def bench_serve(args, pool_size=256, seconds=15.0, fractions=(0.5, 0.7, 0.9), ca
         "capacity_trials": [{k: t[k] for k in ("offered_req_per_s", "achieved_req_per_s", "p99_ms")}
                             for t in trials],
         "burst_capacity_req_per_s": round(burst_rps, 1),
-        "headline": "p50 / p99 at 0.7 C (sweep[0]), C the open-loop capacity; the sweep also has 0.5 and "
-                    f"0.9 C and the fixed rate of {SERVE_FIXED_RATE:.0f} req/s",
+        "headline": f"p50 / p99 at 0.7 C (sweep[0], {head['requests']} requests over about {headline_s:.0f} s), C the "
+                    "open-loop capacity; the sweep also has 0.5 and 0.9 C and the fixed rate of "
+                    f"{SERVE_FIXED_RATE:.0f} req/s (up to 30,000 requests each)",
         "offered_req_per_s": head["offered_req_per_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "p999_ms": head["p999_ms"], "achieved_GBps": head["achieved_GBps"],
         "sweep": runs, "peak_resident_bytes": peak, "overload": overload,
@@ -876,7 +911,8 @@ def bench_serve_child(args, mode=None, overload=True):
     import subprocess
 
     cmd = [sys.executable, "-u", str(Path(__file__).resolve()), "--workload", "serve",
-           "--hw-queues", str(args.serve_hw_queues), "--serve-seconds", str(args.serve_seconds)]
+           "--hw-queues", str(args.serve_hw_queues), "--serve-seconds", str(args.serve_seconds),
+           "--serve-headline-seconds", str(args.serve_headline_seconds)]
     if args.no_overload or not overload:
         cmd.append("--no-overload")
     if args.save_inputs:

@@ -363,6 +363,7 @@ class Server:
         self._h = _vp()
         check(lib().hb_server_create(ctypes.byref(self._h), device, hbm_budget_bytes, max_slots))
         self._live = {}
+        self._trace_raw = None
 
     def submit(self, messages: np.ndarray, offsets: np.ndarray, lengths: np.ndarray, algo=None,
                algos: np.ndarray | None = None) -> int:
@@ -420,6 +421,23 @@ class Server:
         v = (ctypes.c_double * len(self.TRACE_NAMES))()
         check(lib().hb_server_trace(self._h, ticket, v, len(self.TRACE_NAMES)))
         return dict(zip(self.TRACE_NAMES, list(v)))
+
+    def collect(self, ticket: int, trace_out: np.ndarray) -> None:
+        """Wait for a request, write its trace (TRACE_NAMES order) into trace_out (a C-contiguous
+        float64 array of len(TRACE_NAMES)) and release it, with no digest copy or dict built:
+        the low-overhead path for a client that consumes results as they finish.  Raises
+        HBError with the request's status if it failed (after releasing it)."""
+        assert trace_out.dtype == np.float64 and trace_out.size >= len(self.TRACE_NAMES) and trace_out.flags.c_contiguous
+        if self._trace_raw is None:
+            self._trace_raw = lib()["hb_server_trace"]  # a second prototype taking a plain address
+            self._trace_raw.argtypes = [_vp, _u64, _vp, _i]
+        st = _i()
+        check(lib().hb_server_wait(self._h, ticket, -1, ctypes.byref(st)))
+        self._live.pop(ticket, None)
+        rc = self._trace_raw(self._h, ticket, trace_out.ctypes.data, len(self.TRACE_NAMES))
+        check(lib().hb_server_release(self._h, ticket))
+        check(rc)
+        check(st.value)
 
     def stats(self) -> dict:
         v = [_u64() for _ in range(4)]

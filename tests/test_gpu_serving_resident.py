@@ -125,3 +125,45 @@ def test_resident_host_ends_the_wait(hb, resident, monkeypatch):
     t0 = time.perf_counter()
     srv.close()  # the kernel is still inside its idle window: the stop flag ends it
     assert time.perf_counter() - t0 < 2.0
+
+
+@pytest.mark.parametrize("mode", ["steps", "resident"])
+def test_collect_traces_and_releases(hb, monkeypatch, mode):
+    """Server.collect (wait, trace into an array, release): the trace it writes is the one
+    hb_server_trace reports, ordered in time; the record is gone afterwards; a cancelled
+    request's status is raised after its record is released."""
+    monkeypatch.setenv("HB_SERVER_MODE", mode)
+    reqs = _requests(12, seed=33)
+    print(f"case collect {mode}", flush=True)
+    srv = hb.Server(hbm_budget_bytes=1 << 30, max_slots=16)
+    tickets = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in reqs]
+    rows = np.zeros((len(tickets), len(srv.TRACE_NAMES)))
+    for k, t in enumerate(tickets):
+        srv.collect(t, rows[k])
+        tm = dict(zip(srv.TRACE_NAMES, rows[k]))
+        assert tm["submit"] <= tm["admit"] <= tm["stage_begin"] <= tm["stage_end"] <= tm["done"]
+        assert tm["exec_begin"] <= tm["exec_end"] <= tm["done"] + 1e-3
+        with pytest.raises(hb.HBError):
+            srv.trace(t)  # released
+    assert srv.stats()["completed"] == len(reqs)
+    srv.close()
+    # requests queued behind a tiny budget, some cancelled before admission: collect raises
+    # HB_ECANCELED for those, and every record is released either way
+    rng = np.random.default_rng(34)
+    lens = [rng.integers(2000, 6000, size=200).astype(np.uint64) for _ in range(12)]
+    srv = hb.Server(hbm_budget_bytes=2 << 20, max_slots=2)
+    tickets = [srv.submit(workloads.host_random_bytes(int(L.sum()), 700 + k), workloads.packed(L), L, algo=k % 3)
+               for k, L in enumerate(lens)]
+    cancelled = {t for t in tickets[6::2] if srv.cancel(t)}
+    row = np.zeros(len(srv.TRACE_NAMES))
+    for t in tickets:
+        if t in cancelled:
+            with pytest.raises(hb.HBError) as e:
+                srv.collect(t, row)
+            assert e.value.status == hb.HB_ECANCELED
+        else:
+            srv.collect(t, row)
+        with pytest.raises(hb.HBError):
+            srv.trace(t)
+    assert cancelled
+    srv.close()
