@@ -209,8 +209,8 @@ __global__ __launch_bounds__(kServeThreads) void k_serve(ServeRings R, uint32_t 
         h = bcast64(h);
         if (h < t) {
             // claim one item, or up to kMaxClaim when a backlog has built up: the acquire
-            // and release below are cache-wide operations of the XCD's L2, and under load
-            // they, not the hashing, bound the items per second
+            // below is a cache-wide operation of the XCD's L2 (an invalidate), and under
+            // load claims, not the hashing, bound the items per second
             const uint64_t backlog = t - h;
             uint64_t take = backlog >= 32u * kMaxClaim ? kMaxClaim : (backlog >= 64u ? backlog / 32u : 1u);
             if (take > 1) {
