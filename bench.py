@@ -150,11 +150,18 @@ def record_traffic(fetch_dir: str, write_dir: str):
                      "the counters were taken.",
            "read_factor": rf, "write_factor": wf}
     for a, name in enumerate(ALGO_NAMES):
-        k = next(k for k in fetch if f"hb::k_plain<{a}, true>" in k)
-        fb = sum(fetch[k]) / len(fetch[k]) * rf
-        wb = sum(write[k]) / len(write[k]) * wf
-        out[f"fixed:{name}"] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "source_hash": kernel_source_hash(),
-                                "bytes_per_launch": round(fb + wb), "read_over_payload": round(fb / (1 << 30), 3)}
+        # the default plain kernel (MD5: LDS-staged; SHA-1, SM3: per lane) and the alternative
+        kernels = {"fixed": f"hb::k_plain_lds<{a}>" if a == 0 else f"hb::k_plain<{a}, true>",
+                   "fixed_alt": f"hb::k_plain<{a}, true>" if a == 0 else f"hb::k_plain_lds<{a}>"}
+        for key, kname in kernels.items():
+            k = next((k for k in fetch if kname in k), None)
+            if k is None or k not in write:
+                continue
+            fb = sum(fetch[k]) / len(fetch[k]) * rf
+            wb = sum(write[k]) / len(write[k]) * wf
+            out[f"{key}:{name}"] = {"kernel": kname, "fetch_bytes": round(fb), "write_bytes": round(wb),
+                                    "source_hash": kernel_source_hash(), "bytes_per_launch": round(fb + wb),
+                                    "read_over_payload": round(fb / (1 << 30), 3)}
     TRAFFIC_FILE.write_text(json.dumps(out, indent=1) + "\n")
     print(json.dumps(out, indent=1))
 
@@ -180,8 +187,9 @@ def cpu_baseline_fixed(msgs_dev, n, L, target_s, gpu_digests=None):
                 raise RuntimeError(f"{ALGO_NAMES[a]}: {bad.size} of {n} digests differ from the oracle "
                                    f"(first at message {int(bad[0])})")
         verified = {"messages": n * len(gpu_digests), "all_equal_to_oracle": True,
-                    "what": "every digest of the timed launches (each algorithm, default and LDS-staged "
-                            "kernels) against the oracle over the whole buffer",
+                    "what": "every digest of the timed launches (each algorithm's default plain kernel) against "
+                            "the oracle over the whole buffer; the alternative plain kernel's digests are compared "
+                            "with these on the GPU",
                     "seconds": round(time.perf_counter() - t0, 2)}
         del whole
     host = msgs_dev[: min(n, 1 << 16) * L].cpu().numpy()
@@ -272,14 +280,15 @@ def bench_fixed(args):
             "alu_frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
             "hbm_frac_payload": round(payload / t / 1e9 / HBM_PEAK_GBS, 4),
         }
-    # each algorithm again with its message words staged through LDS (HB_PLAIN_LDS=1,
-    # coalesced loads, the same digests): the variant kept as an option, reported beside
-    # the default
+    # each algorithm again with the other plain kernel (the same digests): MD5's default is
+    # the LDS-staged kernel, so its alternative is the per-lane one (HB_PLAIN_LDS=0); SHA-1
+    # and SM3 run per lane by default, their alternative staged through LDS (HB_PLAIN_LDS=1)
     default_digests = {a: outs[a].clone() for a in range(3)}
-    os.environ["HB_PLAIN_LDS"] = "1"
-    try:
-        for a in range(3):
-            lds_ms = []
+    for a in range(3):
+        alt = "per_lane" if a == 0 else "lds_staged"
+        os.environ["HB_PLAIN_LDS"] = "0" if a == 0 else "1"
+        try:
+            alt_ms = []
             for k in range(args.warmup + args.steps):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -287,18 +296,19 @@ def bench_fixed(args):
                 e1.record(stream)
                 e1.synchronize()
                 if k >= args.warmup:
-                    lds_ms.append(e0.elapsed_time(e1))
-            per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms"] = round(float(np.mean(lds_ms)), 4)
-            per_algo[ALGO_NAMES[a]]["lds_staged_kernel_ms_min"] = round(float(np.min(lds_ms)), 4)
-            if not torch.equal(outs[a], default_digests[a]):
-                raise RuntimeError(f"{ALGO_NAMES[a]}: LDS-staged digests differ from the default kernel's")
-    finally:
-        del os.environ["HB_PLAIN_LDS"]
+                    alt_ms.append(e0.elapsed_time(e1))
+        finally:
+            del os.environ["HB_PLAIN_LDS"]
+        per_algo[ALGO_NAMES[a]]["kernel"] = "lds_staged" if a == 0 else "per_lane"
+        per_algo[ALGO_NAMES[a]][f"{alt}_kernel_ms"] = round(float(np.mean(alt_ms)), 4)
+        per_algo[ALGO_NAMES[a]][f"{alt}_kernel_ms_min"] = round(float(np.min(alt_ms)), 4)
+        if not torch.equal(outs[a], default_digests[a]):
+            raise RuntimeError(f"{ALGO_NAMES[a]}: the {alt} kernel's digests differ from the default kernel's")
     dom = max(kms, key=kms.get)
     t_dom = kms[dom] / 1e3
     ops_dom = blocks * OPS_PER_BLOCK[dom]
     traffic = measured_traffic(dom, "fixed")
-    roofline = {"kernel": f"k_plain<{dom},fixed>", "bound": "alu", "achieved": round(ops_dom / t_dom / 1e12, 3),
+    roofline = {"kernel": "k_plain_lds<md5>" if dom == "md5" else f"k_plain<{dom},fixed>", "bound": "alu", "achieved": round(ops_dom / t_dom / 1e12, 3),
                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
                 "frac": round(ops_dom / t_dom / 1e12 / ALU_PEAK_TOPS, 4), "traffic": traffic,
                 "ops_per_launch": ops_dom, "ops_per_block": OPS_PER_BLOCK[dom], "blocks_per_launch": blocks}

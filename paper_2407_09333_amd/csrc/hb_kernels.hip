@@ -53,21 +53,24 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(const uint8_t *__restrict
     store_digest<A>(out + i * stride, s, stride);
 }
 
-// Fixed-length batch with message words staged through LDS (opt-in, HB_PLAIN_LDS=1).  Each
-// wave owns 64 consecutive messages.  Two whole blocks of all 64 go per burst: eight
-// 16-byte loads per lane, lane (q, p) of load j taking chunk p ^ q of message 8j + q, so
-// each load instruction reads eight whole 128-byte lines; the chunks are written to the
-// wave's LDS slice in that order and each lane reads back its own message's 128 bytes, the
-// XOR swizzle putting eight consecutive lanes on eight different bank groups.  The next
-// burst's loads are in flight while the current one is compressed.  Messages must start on
-// a dword (msgs and msg_len 4-byte aligned); the last one or two blocks and a partial last
-// wave go through the per-lane path.  Measured on 2^20 x 1 KiB MD5: 4x fewer L1 accesses,
-// read traffic 1.00x the payload, VALU busy 0.86 against 0.76, but the same time within 1 %:
-// the kernel runs at the HBM read rate either way.
+// Fixed-length batch with message words staged through LDS (MD5's default; SHA-1 and SM3
+// with HB_PLAIN_LDS=1).  Each wave owns 64 consecutive messages.  Two whole blocks of all
+// 64 go per burst: eight 16-byte loads per lane, lane (q, p) of load j taking chunk p ^ q of
+// message 8j + q, so each load instruction reads eight whole 128-byte lines; the chunks are
+// written to the wave's LDS slice in that order and each lane reads back its own message's
+// 128 bytes, the XOR swizzle putting eight consecutive lanes on eight different bank
+// groups.  Messages must start on a dword (msgs and msg_len 4-byte aligned); the last one or
+// two blocks and a partial last wave go through the per-lane path.  MD5, whose reads and
+// compression take about as long as each other, streams: non-temporal loads (every line is
+// read once, whole, by one instruction) with the next two bursts in flight -- on 2^20 x
+// 1 KiB 3-4 % faster than the per-lane kernel in interleaved runs.  SHA-1 and SM3 are bound
+// by their compression: cached loads, one burst ahead (1-2 % slower than per-lane, so not
+// their default).
 template <int A>
 __global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
                                                            uint64_t len, uint8_t *__restrict__ out)
 {
+    constexpr bool kStream = A == MD5;
     __shared__ u32x4 slice[kPlainBlock / 64][512];  // per wave: 64 messages x 128 bytes
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u), lane = threadIdx.x % 64u;
     const uint64_t m0 = (uint64_t(xcd_contiguous_block()) * (kPlainBlock / 64) + wave) * 64u;
@@ -80,19 +83,21 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__rest
     u32x4 *mine = slice[wave];
     uint32_t s[8];
     init_state<A>(s);
-    u32x4 pre[8];
-    auto load = [&](uint64_t k) {
+    auto load = [&](u32x4 *pre, uint64_t k) {
         const uint8_t *bk = wbase + k * 128u;
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            pre[j] = *reinterpret_cast<const HB_GLOBAL u32x4 *>(
+        for (int j = 0; j < 8; ++j) {
+            const HB_GLOBAL u32x4 *a = reinterpret_cast<const HB_GLOBAL u32x4 *>(
                 reinterpret_cast<uintptr_t>(bk + (voff + uint32_t(8 * j) * uint32_t(len))));
+            if constexpr (kStream) pre[j] = __builtin_nontemporal_load(a);
+            else pre[j] = *a;
+        }
     };
-    if (nburst) load(0);
-    for (uint64_t k = 0; k < nburst; ++k) {
+    auto stage = [&](const u32x4 *pre) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) mine[j * 64 + lane] = pre[j];
-        if (k + 1 < nburst) load(k + 1);
+    };
+    auto burst = [&]() {  // the two staged blocks of this lane's message
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             uint32_t w[16];
@@ -105,6 +110,31 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__rest
 #pragma unroll
                 for (int i = 0; i < 16; ++i) w[i] = bswap32(w[i]);
             compress<A>(s, w);
+        }
+    };
+    // A wave's LDS operations complete in order, so a burst's writes to the slice follow the
+    // previous burst's reads of it.
+    if constexpr (kStream) {
+        u32x4 pa[8], pb[8];  // bursts k and k + 1 in flight while k - 1 is compressed
+        if (nburst) load(pa, 0);
+        if (nburst > 1) load(pb, 1);
+        for (uint64_t k = 0; k < nburst; k += 2) {
+            stage(pa);
+            if (k + 2 < nburst) load(pa, k + 2);
+            burst();
+            if (k + 1 < nburst) {
+                stage(pb);
+                if (k + 3 < nburst) load(pb, k + 3);
+                burst();
+            }
+        }
+    } else {
+        u32x4 pre[8];
+        if (nburst) load(pre, 0);
+        for (uint64_t k = 0; k < nburst; ++k) {
+            stage(pre);
+            if (k + 1 < nburst) load(pre, k + 1);
+            burst();
         }
     }
     const uint64_t mi = m0 + lane;
@@ -228,8 +258,9 @@ static hipError_t launch_lds_a(const uint8_t *msgs, uint64_t n, uint64_t len, ui
 
 bool plain_lds_applies(const uint8_t *msgs, uint64_t fixed_len, uint32_t stride, int algo)
 {
+    // MD5 by default, SHA-1 and SM3 with HB_PLAIN_LDS=1; HB_PLAIN_LDS=0 keeps all three per-lane
     const char *v = std::getenv("HB_PLAIN_LDS");
-    if (!v || std::atoi(v) == 0) return false;
+    if (!(v ? std::atoi(v) != 0 : algo == MD5)) return false;
     // dword-aligned messages; 64 messages' offsets fit the loads' 32-bit offsets; packed digests
     return (reinterpret_cast<uintptr_t>(msgs) & 3u) == 0 && fixed_len % 4u == 0 && fixed_len > 0 &&
            fixed_len < (1ull << 25) && stride == uint32_t(digest_size(algo));
