@@ -308,16 +308,20 @@ typedef struct hb_server hb_server;
  * with more hardware queues than HIP's default four); HB_SERVER_LONG_PLAN_FLAGS the
  * long-chain steps' plan flags (default HB_PLAN_LONG_INLINE: the long-chain path of
  * hb_plan_create in one launch; 0: with a side stream; HB_PLAN_NO_LONG: none);
- * HB_SERVER_COPY_STREAMS copy streams (default 1, or 2 with GPU_MAX_HW_QUEUES >= 8);
- * HB_SERVER_COPY=kernel copies payload by kernel from the rings' device mapping, not the
- * copy engine.  A request arriving while others run starts as soon as memory and a slot free up,
- * and its work overlaps theirs on the device.
+ * HB_SERVER_COPY_STREAMS copy streams (default 1, or 2 with GPU_MAX_HW_QUEUES >= 8; one
+ * copy stream carries about 20-25 GB/s of payload, so a serving process is best started with
+ * GPU_MAX_HW_QUEUES=8); HB_SERVER_COPY=kernel copies payload by kernel from the rings'
+ * device mapping, not the copy engine.  A request arriving while others run starts as soon
+ * as memory and a slot free up, and its work overlaps theirs on the device.
  * HB_SERVER_MODE=resident replaces the steps with one resident serving kernel that requests
  * join while it runs: as soon as a request's payload has landed, its work items (up to 64
  * messages of one algorithm, ordered by algorithm and block count) go into a ring in
  * pinned host memory; the kernel's first wave copies them into device memory and its other
- * waves claim them (several at once when a backlog has built up), hash them and write the
- * digests and a done flag straight to pinned host memory.  The kernel leaves after 5 ms
+ * waves claim them (several at once when a backlog has built up, while their longest
+ * messages sum to at most 64 blocks), hash them -- items of up to 4 long messages, which the
+ * loop forms from each algorithm's longest messages while few items are outstanding
+ * (HB_SERVER_RESIDENT_LATENCY_ITEMS, default half the worker waves), with the whole wave on
+ * each chain -- and write the digests and a done flag straight to pinned host memory.  The kernel leaves after 5 ms
  * without items (HB_SERVER_RESIDENT_IDLE_MS) or when the server is destroyed, and the loop
  * starts it again when items wait; one workgroup per two CUs (HB_SERVER_RESIDENT_WGS sets the
  * count: with one on every CU the payload copies, kernels themselves, lag at high load).  While it
