@@ -150,9 +150,8 @@ def record_traffic(fetch_dir: str, write_dir: str):
                      "the counters were taken.",
            "read_factor": rf, "write_factor": wf}
     for a, name in enumerate(ALGO_NAMES):
-        # the default plain kernel (MD5: LDS-staged; SHA-1, SM3: per lane) and the alternative
-        kernels = {"fixed": f"hb::k_plain_lds<{a}>" if a == 0 else f"hb::k_plain<{a}, true>",
-                   "fixed_alt": f"hb::k_plain<{a}, true>" if a == 0 else f"hb::k_plain_lds<{a}>"}
+        # the default plain kernel (LDS-staged) and the alternative (per lane)
+        kernels = {"fixed": f"hb::k_plain_lds<{a}>", "fixed_alt": f"hb::k_plain<{a}, true>"}
         for key, kname in kernels.items():
             k = next((k for k in fetch if kname in k), None)
             if k is None or k not in write:
@@ -280,13 +279,12 @@ def bench_fixed(args):
             "alu_frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
             "hbm_frac_payload": round(payload / t / 1e9 / HBM_PEAK_GBS, 4),
         }
-    # each algorithm again with the other plain kernel (the same digests): MD5's default is
-    # the LDS-staged kernel, so its alternative is the per-lane one (HB_PLAIN_LDS=0); SHA-1
-    # and SM3 run per lane by default, their alternative staged through LDS (HB_PLAIN_LDS=1)
+    # each algorithm again with the other plain kernel (the same digests): the default is the
+    # LDS-staged kernel, the alternative the per-lane one (HB_PLAIN_LDS=0)
     default_digests = {a: outs[a].clone() for a in range(3)}
     for a in range(3):
-        alt = "per_lane" if a == 0 else "lds_staged"
-        os.environ["HB_PLAIN_LDS"] = "0" if a == 0 else "1"
+        alt = "per_lane"
+        os.environ["HB_PLAIN_LDS"] = "0"
         try:
             alt_ms = []
             for k in range(args.warmup + args.steps):
@@ -299,7 +297,7 @@ def bench_fixed(args):
                     alt_ms.append(e0.elapsed_time(e1))
         finally:
             del os.environ["HB_PLAIN_LDS"]
-        per_algo[ALGO_NAMES[a]]["kernel"] = "lds_staged" if a == 0 else "per_lane"
+        per_algo[ALGO_NAMES[a]]["kernel"] = "lds_staged"
         per_algo[ALGO_NAMES[a]][f"{alt}_kernel_ms"] = round(float(np.mean(alt_ms)), 4)
         per_algo[ALGO_NAMES[a]][f"{alt}_kernel_ms_min"] = round(float(np.min(alt_ms)), 4)
         if not torch.equal(outs[a], default_digests[a]):
@@ -308,7 +306,7 @@ def bench_fixed(args):
     t_dom = kms[dom] / 1e3
     ops_dom = blocks * OPS_PER_BLOCK[dom]
     traffic = measured_traffic(dom, "fixed")
-    roofline = {"kernel": "k_plain_lds<md5>" if dom == "md5" else f"k_plain<{dom},fixed>", "bound": "alu", "achieved": round(ops_dom / t_dom / 1e12, 3),
+    roofline = {"kernel": f"k_plain_lds<{dom}>", "bound": "alu", "achieved": round(ops_dom / t_dom / 1e12, 3),
                 "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
                 "frac": round(ops_dom / t_dom / 1e12 / ALU_PEAK_TOPS, 4), "traffic": traffic,
                 "ops_per_launch": ops_dom, "ops_per_block": OPS_PER_BLOCK[dom], "blocks_per_launch": blocks}

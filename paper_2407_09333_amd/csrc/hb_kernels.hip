@@ -53,21 +53,28 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(const uint8_t *__restrict
     store_digest<A>(out + i * stride, s, stride);
 }
 
-// Fixed-length batch with message words staged through LDS (MD5's default; SHA-1 and SM3
-// with HB_PLAIN_LDS=1).  Each wave owns 64 consecutive messages.  Two whole blocks of all
-// 64 go per burst: eight 16-byte loads per lane, lane (q, p) of load j taking chunk p ^ q of
-// message 8j + q, so each load instruction reads eight whole 128-byte lines; the chunks are
-// written to the wave's LDS slice in that order and each lane reads back its own message's
-// 128 bytes, the XOR swizzle putting eight consecutive lanes on eight different bank
-// groups.  Messages must start on a dword (msgs and msg_len 4-byte aligned); the last one or
-// two blocks and a partial last wave go through the per-lane path.  MD5, whose reads and
+// Buffer resource word 3 for raw (unswizzled, unformatted) dword access on gfx9-family
+// GPUs, and the cache-policy bit of a non-temporal buffer load.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+constexpr int kCpolNonTemporal = 2;
+
+// Fixed-length batch with message words staged through LDS (the default for dword-aligned
+// fixed-length batches; HB_PLAIN_LDS=0 takes k_plain instead).  Each wave owns 64
+// consecutive messages.  Two whole blocks of all 64 go per burst: eight 16-byte loads per
+// lane, lane (q, p) of load j taking chunk p ^ q of message 8j + q, so each load instruction
+// reads eight whole 128-byte lines; the chunks are written to the wave's LDS slice in that
+// order and each lane reads back its own message's 128 bytes, the XOR swizzle putting eight
+// consecutive lanes on eight different bank groups.  Messages must start on a dword (msgs
+// and msg_len 4-byte aligned); the last one or two blocks and a partial last wave go through
+// the per-lane path.  The loads are buffer loads off one wave-uniform base, so they take no
+// vector address arithmetic (MD5 issues its 324 compression instructions per block and
+// nothing more) and few registers: four waves per SIMD for all three.  MD5, whose reads and
 // compression take about as long as each other, streams: non-temporal loads (every line is
-// read once, whole, by one instruction) with the next two bursts in flight -- on 2^20 x
-// 1 KiB 3-4 % faster than the per-lane kernel in interleaved runs.  SHA-1 and SM3 are bound
-// by their compression: cached loads, one burst ahead (1-2 % slower than per-lane, so not
-// their default).
+// read once, whole, by one instruction) with the next two bursts in flight.  SHA-1 and SM3
+// are bound by their compression: cached loads, one burst ahead.  In interleaved runs on
+// 2^20 x 1 KiB against the per-lane kernel: MD5 0.95, SHA-1 and SM3 0.985 of its time.
 template <int A>
-__global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
+__global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
                                                            uint64_t len, uint8_t *__restrict__ out)
 {
     constexpr bool kStream = A == MD5;
@@ -83,50 +90,93 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__rest
     u32x4 *mine = slice[wave];
     uint32_t s[8];
     init_state<A>(s);
+    // The wave's 64 messages through one buffer resource: base in SGPRs, the lane's 32-bit
+    // offset in one VGPR, the burst's and load's offset (k 128 + 8 j len) in an SGPR, so a
+    // load costs no vector address arithmetic and the loop keeps no 64-bit addresses.  The
+    // range (2^32 - 1 bytes) covers every offset: 64 len < 2^31 for the lengths taken here.
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(wbase), 0, -1, kBufferRsrcWord3);
     auto load = [&](u32x4 *pre, uint64_t k) {
-        const uint8_t *bk = wbase + k * 128u;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const HB_GLOBAL u32x4 *a = reinterpret_cast<const HB_GLOBAL u32x4 *>(
-                reinterpret_cast<uintptr_t>(bk + (voff + uint32_t(8 * j) * uint32_t(len))));
-            if constexpr (kStream) pre[j] = __builtin_nontemporal_load(a);
-            else pre[j] = *a;
-        }
+        for (int j = 0; j < 8; ++j)
+            pre[j] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, uint32_t(k * 128u + uint64_t(8 * j) * len),
+                                                           kStream ? kCpolNonTemporal : 0);
     };
     auto stage = [&](const u32x4 *pre) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) mine[j * 64 + lane] = pre[j];
     };
-    auto burst = [&]() {  // the two staged blocks of this lane's message
+    // The two staged blocks of this lane's message.  MD5 and SHA-1 read both blocks' words
+    // from LDS up front, so the second block's reads complete under the first block's
+    // compression (16 more registers; SM3, with more state live, reads one block at a time
+    // to stay within four waves per SIMD).
+    constexpr bool kReadAhead = A != SM3;
+    auto words = [&](int h, uint32_t *w) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            uint32_t w[16];
+        for (int i = 0; i < 4; ++i) {
+            const u32x4 v = mine[lane * 8u + ((4u * h + i) ^ sw)];
+            w[4 * i] = v.x; w[4 * i + 1] = v.y; w[4 * i + 2] = v.z; w[4 * i + 3] = v.w;
+        }
+        if (Traits<A>::kBE)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const u32x4 v = mine[lane * 8u + ((4u * h + i) ^ sw)];
-                w[4 * i] = v.x; w[4 * i + 1] = v.y; w[4 * i + 2] = v.z; w[4 * i + 3] = v.w;
+            for (int i = 0; i < 16; ++i) w[i] = bswap32(w[i]);
+    };
+    auto burst = [&]() {
+        if constexpr (kReadAhead) {
+            uint32_t w0[16], w1[16];
+            // block 0's reads, then block 1's, both before block 0's compression: the wait
+            // for block 0 leaves block 1's reads in flight under it
+            words(0, w0);
+            __builtin_amdgcn_sched_barrier(0);
+            words(1, w1);
+            __builtin_amdgcn_sched_barrier(0);
+            compress<A>(s, w0);
+            compress<A>(s, w1);
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t w[16];
+                words(h, w);
+                compress<A>(s, w);
             }
-            if (Traits<A>::kBE)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) w[i] = bswap32(w[i]);
-            compress<A>(s, w);
         }
     };
     // A wave's LDS operations complete in order, so a burst's writes to the slice follow the
     // previous burst's reads of it.
     if constexpr (kStream) {
-        u32x4 pa[8], pb[8];  // bursts k and k + 1 in flight while k - 1 is compressed
-        if (nburst) load(pa, 0);
-        if (nburst > 1) load(pb, 1);
-        for (uint64_t k = 0; k < nburst; k += 2) {
-            stage(pa);
-            if (k + 2 < nburst) load(pa, k + 2);
-            burst();
-            if (k + 1 < nburst) {
+        // bursts k + 1 and k + 2 in flight while k is compressed.  The steady-state loop's
+        // loads are unconditional: a load under a branch makes the compiler's wait before a
+        // stage count it as possibly outstanding, so each loop top waited for both buffers
+        // and the second burst had only one burst of compression to arrive in.
+        u32x4 pa[8], pb[8];
+        if (nburst >= 2) {
+            load(pa, 0);
+            __builtin_amdgcn_sched_barrier(0);  // pa's loads issue before pb's, as in the loop
+            load(pb, 1);
+            uint64_t k = 0;
+            for (; k + 4 <= nburst; k += 2) {
+                stage(pa);
+                load(pa, k + 2);
+                burst();
                 stage(pb);
-                if (k + 3 < nburst) load(pb, k + 3);
+                load(pb, k + 3);
                 burst();
             }
+            // bursts k and k + 1 are in flight; at most one more remains
+            const bool odd = k + 3 == nburst;
+            stage(pa);
+            if (odd) load(pa, k + 2);
+            burst();
+            stage(pb);
+            burst();
+            if (odd) {
+                stage(pa);
+                burst();
+            }
+        } else if (nburst == 1) {
+            load(pa, 0);
+            stage(pa);
+            burst();
         }
     } else {
         u32x4 pre[8];
@@ -140,11 +190,30 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_lds(const uint8_t *__rest
     const uint64_t mi = m0 + lane;
     if (mi >= n) return;
     const Msg m = make_msg<A>(msgs + mi * len, len);
-    for (uint64_t blk = nburst * 2u; blk < nb; ++blk) {
+    uint64_t blk = nburst * 2u;
+    for (; blk < nfast; ++blk) {
         uint32_t w[16];
-        if (blk < nfast) load_full_block(m, blk, w);
-        else load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
+        load_full_block(m, blk, w);
         compress<A>(s, w);
+    }
+    if (len % 64u == 0) {
+        // the last block is padding only -- 0x80, zeros, the bit length -- and the same for
+        // every message of the batch: wave-uniform words, nothing to read or assemble
+        constexpr bool kBE = Traits<A>::kBE;
+        uint32_t w[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) w[i] = 0u;
+        w[0] = kBE ? 0x80000000u : 0x80u;
+        const uint64_t bits = len << 3;
+        w[14] = kBE ? uint32_t(bits >> 32) : uint32_t(bits);
+        w[15] = kBE ? uint32_t(bits) : uint32_t(bits >> 32);
+        compress<A>(s, w);
+    } else {
+        for (; blk < nb; ++blk) {
+            uint32_t w[16];
+            load_any_block<Traits<A>::kBE>(m, blk, blk + 1 == nb, w);
+            compress<A>(s, w);
+        }
     }
     store_digest<A>(out + mi * Traits<A>::kDigest, s, Traits<A>::kDigest);
 }
@@ -258,9 +327,9 @@ static hipError_t launch_lds_a(const uint8_t *msgs, uint64_t n, uint64_t len, ui
 
 bool plain_lds_applies(const uint8_t *msgs, uint64_t fixed_len, uint32_t stride, int algo)
 {
-    // MD5 by default, SHA-1 and SM3 with HB_PLAIN_LDS=1; HB_PLAIN_LDS=0 keeps all three per-lane
+    // all three algorithms by default; HB_PLAIN_LDS=0 keeps them per lane
     const char *v = std::getenv("HB_PLAIN_LDS");
-    if (!(v ? std::atoi(v) != 0 : algo == MD5)) return false;
+    if (v && std::atoi(v) == 0) return false;
     // dword-aligned messages; 64 messages' offsets fit the loads' 32-bit offsets; packed digests
     return (reinterpret_cast<uintptr_t>(msgs) & 3u) == 0 && fixed_len % 4u == 0 && fixed_len > 0 &&
            fixed_len < (1ull << 25) && stride == uint32_t(digest_size(algo));

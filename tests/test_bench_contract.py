@@ -65,21 +65,21 @@ def test_record_traffic_scales_by_the_copy_kernel(tmp_path, monkeypatch):
     plain = "void hb::k_plain<{}, true>(unsigned char const*, unsigned long)"
     lds = "void hb::k_plain_lds<{}>(unsigned char const*, unsigned long, unsigned long, unsigned char*)"
     # the copy kernel reads 1 GiB but the counter says half of it in KiB; a small copy too.
-    # MD5's default plain kernel is the LDS-staged one; the per-lane one is its alternative
+    # The default plain kernel is the LDS-staged one; the per-lane one is the alternative
     write_csv(tmp_path / "fetch", [("__amd_rocclr_copyBuffer", 524288), ("__amd_rocclr_copyBuffer", 10),
                                    (lds.format(0), 512 * 1024), (lds.format(0), 512 * 1024),
                                    (plain.format(0), 520 * 1024),
-                                   (plain.format(1), 600 * 1024), (plain.format(2), 700 * 1024)])
+                                   (lds.format(1), 600 * 1024), (lds.format(2), 700 * 1024)])
     write_csv(tmp_path / "write", [("__amd_rocclr_copyBuffer", 1 << 20), (lds.format(0), 16 * 1024),
                                    (plain.format(0), 16 * 1024),
-                                   (plain.format(1), 20 * 1024), (plain.format(2), 32 * 1024)])
+                                   (lds.format(1), 20 * 1024), (lds.format(2), 32 * 1024)])
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", out)
     bench.record_traffic(str(tmp_path / "fetch"), str(tmp_path / "write"))
     t = json.loads(out.read_text())
     assert t["read_factor"] == 2.0 and t["write_factor"] == 1.0
     assert t["fixed:md5"]["fetch_bytes"] == 1 << 30 and t["fixed:md5"]["write_bytes"] == 16 << 20
-    assert t["fixed:md5"]["kernel"] == "hb::k_plain_lds<0>"
+    assert t["fixed:md5"]["kernel"] == "hb::k_plain_lds<0>" and t["fixed:sm3"]["kernel"] == "hb::k_plain_lds<2>"
     assert t["fixed_alt:md5"]["fetch_bytes"] == 2 * 520 * (1 << 20)
     assert "fixed_alt:sha1" not in t  # no counters for it in this run
     assert t["fixed:sm3"]["bytes_per_launch"] == 2 * 700 * (1 << 20) + (32 << 20)

@@ -43,12 +43,13 @@ def test_fixed_lengths(hb, algo, L):
 
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,L", [(300, 1024), (640, 128), (1000, 4), (515, 132), (4096, 2048), (128, 1028),
-                                 (257, 256), (64, 60), (320, 384), (200, 640)])
+                                 (257, 256), (64, 60), (320, 384), (200, 640), (256, 512), (96, 768),
+                                 (192, 896), (130, 1152)])
 def test_fixed_lds_staged(hb, monkeypatch, algo, n, L):
-    """The LDS-staged fixed-length kernel (HB_PLAIN_LDS=1; MD5's default): whole waves stage
+    """The LDS-staged fixed-length kernel (the default; set explicitly): whole waves stage
     two blocks per burst through LDS, partial waves and the last blocks go per lane; burst
-    counts 0 to 16, odd and even (MD5 keeps two bursts in flight); digests bit-exact against
-    the oracle, and no write outside the digest buffer."""
+    counts 0 to 9 and 16, odd and even, below and inside MD5's two-burst steady-state loop;
+    digests bit-exact against the oracle, and no write outside the digest buffer."""
     monkeypatch.setenv("HB_PLAIN_LDS", "1")
     b = workloads.fixed_batch(algo, n, L, seed=500 + L)
     print(f"case fixed lds algo={algo} n={n} L={L}", flush=True)
@@ -59,17 +60,19 @@ def test_fixed_lds_staged(hb, monkeypatch, algo, n, L):
     assert_same(out.cpu().numpy(), oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), "fixed lds")
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,L", [(300, 1024), (515, 132), (320, 384), (64, 60)])
-def test_fixed_md5_per_lane(hb, monkeypatch, n, L):
-    """MD5 fixed-length batches with HB_PLAIN_LDS=0 take the per-lane kernel (the LDS-staged
-    one is MD5's default): the same digests, bit-exact against the oracle."""
+def test_fixed_per_lane(hb, monkeypatch, algo, n, L):
+    """Fixed-length batches with HB_PLAIN_LDS=0 take the per-lane kernel (the LDS-staged one
+    is the default): the same digests, bit-exact against the oracle."""
     monkeypatch.setenv("HB_PLAIN_LDS", "0")
-    b = workloads.fixed_batch(0, n, L, seed=800 + L)
-    print(f"case fixed md5 per-lane n={n} L={L}", flush=True)
-    buf, out = guarded_out(n, 16)
-    hb.hash_batch_fixed(0, b.messages, n, L, out=out)
-    check_guard(buf, n, 16)
-    assert_same(out.cpu().numpy(), oracle.hash_batch(0, b.messages, b.offsets, b.lengths), "fixed md5 per-lane")
+    b = workloads.fixed_batch(algo, n, L, seed=800 + L)
+    print(f"case fixed per-lane algo={algo} n={n} L={L}", flush=True)
+    ds = oracle.DIGEST_SIZE[algo]
+    buf, out = guarded_out(n, ds)
+    hb.hash_batch_fixed(algo, b.messages, n, L, out=out)
+    check_guard(buf, n, ds)
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), "fixed per-lane")
 
 
 @pytest.mark.parametrize("algo", ALGOS)
