@@ -61,8 +61,31 @@ ALGO_NAMES = ["md5", "sha1", "sm3"]
 # byte order.  MD5's words are little-endian as loaded, so on dword-aligned messages (the
 # fixed-length batches) it needs none: 64 steps x 5 + 4.
 OPS_PER_BLOCK = {"md5": 324, "sha1": 613, "sm3": 1348}
-CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
-ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12     # 39.32 T int32 lane-ops/s
+# The same count split by issue rate: (full-rate, half-rate).  A gfx950 SIMD issues a wave64
+# VALU instruction in 2 cycles for the plain 32-bit ops used here (v_bitop3_b32, VOP2
+# v_add_u32 / v_xor_b32: 32 lanes per clock, the rate behind the 157.3 TFLOP/s fp32 vector
+# peak) and in 4 cycles for the others (v_add3_u32, v_xad_u32, v_alignbit_b32, v_perm_b32).
+#   MD5   per step F, + T, + b (full); add3, rotate (half); 4 final adds (full)
+#   SHA-1 per round f (full); two add3, two rotates (half); per schedule word xor3, xor
+#         (full), rotate (half); 5 final adds (full); 16 perms (half)
+#   SM3   per round FF, GG, P0's xor3, two adds (full); two add3, two xad, six rotates
+#         (half); per expansion word three xor3 (full), four rotates (half); 8 final xors
+#         (full); 16 perms (half)
+OPS_BY_RATE = {"md5": (196, 128), "sha1": (213, 400), "sm3": (484, 864)}
+CUS, SIMDS_PER_CU, LANES, CLOCK_GHZ = 256, 4, 64, 2.4
+# one lane-op per lane per clock (the half-rate class's peak): 39.32 T int32 lane-ops/s
+ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12
+
+
+def mix_peak_tops(name):
+    """Peak lane-op rate for an algorithm's op mix from the unit counts and the clock: every
+    SIMD issuing its full-rate ops in 2 cycles and its half-rate ops in 4 (wave64), no gaps."""
+    full, half = OPS_BY_RATE[name]
+    cycles = 2 * full + 4 * half  # per wave and block, on one SIMD
+    return OPS_PER_BLOCK[name] * LANES * CUS * SIMDS_PER_CU * CLOCK_GHZ * 1e9 / cycles / 1e12
+
+
+ALU_PEAK_MIX_TOPS = {a: mix_peak_tops(a) for a in OPS_PER_BLOCK}  # MD5 56.37, SHA-1 47.59, SM3 47.93
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "traffic.json"
 
@@ -276,7 +299,8 @@ def bench_fixed(args):
             "kernel_ms_min": round(float(np.min(per_step[name])), 4),
             "hashed_GBps": round(payload / t / 1e9, 1),
             "alu_Tops": round(ops / t / 1e12, 2),
-            "alu_frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
+            "alu_frac": round(ops / t / 1e12 / ALU_PEAK_MIX_TOPS[name], 4),
+            "alu_frac_one_op_per_lane_clock": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4),
             "hbm_frac_payload": round(payload / t / 1e9 / HBM_PEAK_GBS, 4),
         }
     # each algorithm again with the other plain kernel (the same digests): the default is the
@@ -307,9 +331,15 @@ def bench_fixed(args):
     ops_dom = blocks * OPS_PER_BLOCK[dom]
     traffic = measured_traffic(dom, "fixed")
     roofline = {"kernel": f"k_plain_lds<{dom}>", "bound": "alu", "achieved": round(ops_dom / t_dom / 1e12, 3),
-                "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
-                "frac": round(ops_dom / t_dom / 1e12 / ALU_PEAK_TOPS, 4), "traffic": traffic,
-                "ops_per_launch": ops_dom, "ops_per_block": OPS_PER_BLOCK[dom], "blocks_per_launch": blocks}
+                "peak": round(ALU_PEAK_MIX_TOPS[dom], 2), "unit": "Tops/s (int32 lane-ops)",
+                "frac": round(ops_dom / t_dom / 1e12 / ALU_PEAK_MIX_TOPS[dom], 4), "traffic": traffic,
+                "ops_per_launch": ops_dom, "ops_per_block": OPS_PER_BLOCK[dom], "blocks_per_launch": blocks,
+                "ops_per_block_full_half_rate": list(OPS_BY_RATE[dom]),
+                "peak_note": "peak for the algorithm's op mix: full-rate ops (bitop3, VOP2 add/xor) 2 cycles, "
+                             "half-rate ops (add3, xad, alignbit, perm) 4 cycles per wave64 instruction per SIMD, "
+                             "1,024 SIMDs at 2.4 GHz",
+                "peak_one_op_per_lane_clock": round(ALU_PEAK_TOPS, 2),
+                "frac_one_op_per_lane_clock": round(ops_dom / t_dom / 1e12 / ALU_PEAK_TOPS, 4)}
     rec = {
         "metric": "hashed GB/s per algo (MD5/SHA-1/SM3), % int-VALU peak; serving p99 ms",
         "value": round(3 * payload / (ms_per_step / 1e3) / 1e9, 1),
@@ -449,8 +479,9 @@ def bench_uneven(args, steps=5, warmup=2):
         "batched_hash_kernel_ms": round(k_ms, 3),
         "plain_ms": round(t_plain, 3), "plain_GBps": round(payload / t_plain / 1e6, 1),
         "speedup_vs_plain": round(t_plain / t_plan, 3),
-        "alu_frac_batched_kernel": round(ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_TOPS, 4),
-        "alu_frac_plain": round(ops / (t_plain / 1e3) / 1e12 / ALU_PEAK_TOPS, 4),
+        "alu_frac_batched_kernel": round(ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_MIX_TOPS["sm3"], 4),
+        "alu_frac_plain": round(ops / (t_plain / 1e3) / 1e12 / ALU_PEAK_MIX_TOPS["sm3"], 4),
+        "alu_frac_batched_kernel_one_op_per_lane_clock": round(ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_TOPS, 4),
         "critical_path_ms_bound": round(_critical_path_ms(b.lengths, None, 2), 3),
         "plan_config": cfg,
         "plan_config_note": "autotuned: waves per CU x messages per lane x load scheme (variant 0 default "
@@ -491,6 +522,9 @@ def bench_mixed(args, steps=3, warmup=1):
     payload = int(b.lengths.sum())
     nb = (b.lengths.astype(np.int64) + 8) // 64 + 1
     ops = int((nb * np.array([OPS_PER_BLOCK[a] for a in ALGO_NAMES])[b.algos]).sum())
+    # the throughput bound: each algorithm's ops at its own mix peak
+    t_peak_s = float(sum((nb[b.algos == k].sum() * OPS_PER_BLOCK[a]) / (ALU_PEAK_MIX_TOPS[a] * 1e12)
+                         for k, a in enumerate(ALGO_NAMES)))
     cp = _critical_path_ms(b.lengths, b.algos, None)
     cp_ro = _critical_path_ms(b.lengths, b.algos, None, per_block=ROUNDS_ONLY_OPS)
     res = {
@@ -501,7 +535,7 @@ def bench_mixed(args, steps=3, warmup=1):
         "fused_ms_min": round(st_plan["min"], 3), "fused_GBps": round(payload / t_plan / 1e6, 1),
         "plain_3_launches_ms": round(t_plain, 3), "plain_GBps": round(payload / t_plain / 1e6, 1),
         "speedup_vs_plain": round(t_plain / t_plan, 3),
-        "throughput_bound_ms": round(ops / (ALU_PEAK_TOPS * 1e12) * 1e3, 3),
+        "throughput_bound_ms": round(t_peak_s * 1e3, 3),
         "critical_path_ms_full_compression": round(cp, 3),
         "critical_path_ms_bound": round(cp_ro, 3),
         "frac_of_critical_path_bound": round(cp_ro / t_plan, 4),

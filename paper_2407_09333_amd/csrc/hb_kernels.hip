@@ -92,10 +92,13 @@ __global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(4))
     init_state<A>(s);
     // The wave's 64 messages through one buffer resource: base in SGPRs, the lane's 32-bit
     // offset in one VGPR, the burst's and load's offset (k 128 + 8 j len) in an SGPR, so a
-    // load costs no vector address arithmetic and the loop keeps no 64-bit addresses.  The
-    // range (2^32 - 1 bytes) covers every offset: 64 len < 2^31 for the lengths taken here.
+    // load costs no vector address arithmetic and the loop keeps no 64-bit addresses.  Its
+    // range is the wave's 64 messages, 64 len bytes (< 2^31 for the lengths taken here):
+    // the furthest load, burst nburst - 1 of message 63, ends at 63 len + 128 nburst <= 64 len,
+    // and a read past the range would return zeros rather than touch other memory.  Only
+    // whole waves (m0 + 64 <= n) use it.
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(wbase), 0, -1, kBufferRsrcWord3);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(wbase), 0, int(64u * uint32_t(len)), kBufferRsrcWord3);
     auto load = [&](u32x4 *pre, uint64_t k) {
 #pragma unroll
         for (int j = 0; j < 8; ++j)

@@ -24,6 +24,13 @@ def test_roofline_constants():
     # the fused op-count floors per 64-byte block; MD5 needs no byte-order perms on the
     # dword-aligned fixed-length batches the roofline is quoted on
     assert bench.OPS_PER_BLOCK == {"md5": 324, "sha1": 613, "sm3": 1348}
+    # the same counts split into full-rate (2 cycles per wave64 instruction) and half-rate
+    # (4 cycles) ops, and the peak each mix gives at 1,024 SIMDs x 2.4 GHz
+    for a, (full, half) in bench.OPS_BY_RATE.items():
+        assert full + half == bench.OPS_PER_BLOCK[a]
+        want = bench.OPS_PER_BLOCK[a] * 64 * 1024 * 2.4e9 / (2 * full + 4 * half) / 1e12
+        assert abs(bench.ALU_PEAK_MIX_TOPS[a] - want) < 1e-9
+    assert abs(bench.ALU_PEAK_MIX_TOPS["sm3"] - 47.93) < 0.01 and abs(bench.ALU_PEAK_MIX_TOPS["md5"] - 56.37) < 0.01
 
 
 def test_critical_path_bound():
