@@ -320,7 +320,7 @@ typedef struct hb_server hb_server;
  * waves claim them (several at once when a backlog has built up, while their longest
  * messages sum to at most 64 blocks), hash them -- items of up to 4 long messages, which the
  * loop forms from each algorithm's longest messages while few items are outstanding
- * (HB_SERVER_RESIDENT_LATENCY_ITEMS, default half the worker waves), with the whole wave on
+ * (HB_SERVER_RESIDENT_LATENCY_ITEMS, default twice the launch's waves), with the whole wave on
  * each chain -- and write the digests and a done flag straight to pinned host memory.  The kernel leaves after 5 ms
  * without items (HB_SERVER_RESIDENT_IDLE_MS) or when the server is destroyed, and the loop
  * starts it again when items wait; one workgroup per two CUs (HB_SERVER_RESIDENT_WGS sets the
