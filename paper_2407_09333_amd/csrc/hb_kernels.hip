@@ -67,12 +67,12 @@ constexpr int kCpolNonTemporal = 2;
 // consecutive lanes on eight different bank groups.  Messages must start on a dword (msgs
 // and msg_len 4-byte aligned); the last one or two blocks and a partial last wave go through
 // the per-lane path.  The loads are buffer loads off one wave-uniform base, so they take no
-// vector address arithmetic (MD5 issues its 324 compression instructions per block and
-// nothing more) and few registers: four waves per SIMD for all three.  MD5, whose reads and
-// compression take about as long as each other, streams: non-temporal loads (every line is
-// read once, whole, by one instruction) with the next two bursts in flight.  SHA-1 and SM3
-// are bound by their compression: cached loads, one burst ahead.  In interleaved runs on
-// 2^20 x 1 KiB against the per-lane kernel: MD5 0.95, SHA-1 and SM3 0.985 of its time.
+// vector address arithmetic (MD5 issues its compression instructions and almost nothing
+// more) and few registers: four or five waves per SIMD.  MD5, whose reads and compression
+// take about as long as each other, streams: non-temporal loads (every line is read once,
+// whole, by one instruction) with the next two bursts in flight.  SHA-1 and SM3 are bound by
+// their compression: cached loads, one burst ahead.  In interleaved runs on 2^20 x 1 KiB
+// against the per-lane kernel: MD5 0.905, SHA-1 0.984, SM3 0.981 of its time.
 template <int A>
 __global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
                                                            uint64_t len, uint8_t *__restrict__ out)

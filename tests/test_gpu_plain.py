@@ -61,6 +61,29 @@ def test_fixed_lds_staged(hb, monkeypatch, algo, n, L):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("shift", [4, 8, 12])
+@pytest.mark.parametrize("L", [1024, 1028])
+def test_fixed_lds_staged_base_off_16_bytes(hb, algo, shift, L):
+    """A fixed-length batch whose buffer starts 4, 8 or 12 bytes past a 16-byte boundary (a
+    view into a larger device buffer): the LDS-staged kernel's 16-byte buffer loads fall on
+    dword-aligned addresses only; digests bit-exact against the oracle."""
+    import torch
+
+    n = 200
+    b = workloads.fixed_batch(algo, n, L, seed=900 + shift + L)
+    big = torch.zeros(n * L + 64, dtype=torch.uint8, device="cuda")
+    big[shift:shift + n * L] = torch.from_numpy(b.messages).cuda()
+    view = big[shift:shift + n * L]
+    assert view.data_ptr() % 16 == shift
+    print(f"case fixed lds shifted base algo={algo} shift={shift} L={L}", flush=True)
+    ds = oracle.DIGEST_SIZE[algo]
+    buf, out = guarded_out(n, ds)
+    hb.hash_batch_fixed(algo, view, n, L, out=out)
+    check_guard(buf, n, ds)
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, b.messages, b.offsets, b.lengths), "fixed lds shifted")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,L", [(300, 1024), (515, 132), (320, 384), (64, 60)])
 def test_fixed_per_lane(hb, monkeypatch, algo, n, L):
     """Fixed-length batches with HB_PLAIN_LDS=0 take the per-lane kernel (the LDS-staged one
