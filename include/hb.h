@@ -74,7 +74,10 @@ int hash_batch_strided(int algo, const uint8_t *messages, const uint64_t *offset
 /*
  * hash_batch_fixed -- n messages of exactly msg_len bytes stored back to back:
  * message i is messages[i * msg_len .. (i + 1) * msg_len).  No metadata arrays are read.
- * digests_out holds n slots of hb_digest_size(algo) bytes.  Allocates nothing.
+ * digests_out holds n slots of hb_digest_size(algo) bytes.  Allocates nothing.  When
+ * messages and msg_len are multiples of 4 and msg_len < 2^25, each wave of 64 messages
+ * stages two blocks of all 64 at a time through LDS with whole-line loads (HB_PLAIN_LDS=0
+ * reads each lane's message on its own instead); either way the digests are the same.
  */
 int hash_batch_fixed(int algo, const uint8_t *messages, uint64_t n, uint64_t msg_len,
                      uint8_t *digests_out, void *stream);
