@@ -96,7 +96,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="fixed",
-                   choices=["fixed", "uneven", "mixed", "serve", "digits9", "ingest", "incremental"])
+                   choices=["fixed", "uneven", "mixed", "serve", "digits9", "ingest", "incremental", "valu"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time in total")
     p.add_argument("--only-headline", action="store_true",
@@ -244,6 +244,27 @@ def cpu_baseline_fixed(msgs_dev, n, L, target_s, gpu_digests=None):
             "paper_context": "the paper reports only ratios: its best CPU+GPU split over OpenSSL with OpenMP "
                              "on all CPU threads, SHA-1 55.8x, MD5 1.2x, SM3 22.5x (Sec. V-B, other "
                              "hardware and baseline); per_algo here is the plain C oracle"}
+
+
+def bench_valu_probe():
+    """The integer-VALU issue rates the roofline's peak rests on (hb_probe_valu): SIMD cycles
+    per wave instruction for each instruction kind and two mixes, and per wave and 64-byte
+    block for each algorithm's compression from registers, at 1, 4 and 8 waves per SIMD (one
+    wave alone shows a lone chain's issue limit); beside them the op-mix model (2 cycles per
+    full-rate op, 4 per half-rate op) and the fraction of it each compression reaches."""
+    from paper_2407_09333_amd import hb
+
+    out = {"unit": "SIMD cycles per wave instruction (md5/sha1/sm3: per wave and 64-byte block)"}
+    for wps in (1, 4, 8):
+        out[f"waves_per_simd_{wps}"] = {}
+        for k in hb.PROBE_KINDS:
+            c, g = hb.probe_valu(k, wps)
+            out[f"waves_per_simd_{wps}"][k] = {"cycles": round(c, 3), "clock_ghz": round(g, 3)}
+    model = {a: 2 * f + 4 * h for a, (f, h) in OPS_BY_RATE.items()}
+    out["mix_model_cycles_per_block"] = model
+    out["compression_frac_of_mix_peak_at_4_waves"] = {
+        a: round(model[a] / out["waves_per_simd_4"][a]["cycles"], 3) for a in ALGO_NAMES}
+    return out
 
 
 def bench_fixed(args):
@@ -1049,6 +1070,8 @@ def main():
             rec["paper_workload_digits9"] = bench_digits9(args)
             print("bench: incremental hashing", file=sys.stderr, flush=True)
             rec["incremental"] = bench_incremental(args)
+            print("bench: integer-VALU issue rates", file=sys.stderr, flush=True)
+            rec["valu_issue_rates"] = bench_valu_probe()
             rec["serving"] = serving
             rec["serving_resident"] = serving_resident
             rec["serving_summary"] = _serve_summary({"steps": serving, "resident": serving_resident})
@@ -1060,6 +1083,8 @@ def main():
         rec = {"ingest_host_resident": bench_ingest(args)}
     elif args.workload == "incremental":
         rec = {"incremental": bench_incremental(args)}
+    elif args.workload == "valu":
+        rec = {"valu_issue_rates": bench_valu_probe()}
     elif args.workload == "digits9":
         rec = {"paper_workload_digits9": bench_digits9(args)}
     else:

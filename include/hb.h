@@ -51,6 +51,30 @@ const char *hb_last_error(void);
 int hb_device_info(int *cu_count, int *wave_size, int *clock_khz, char *arch_name, size_t arch_len);
 
 /*
+ * hb_probe_valu -- measures the integer-VALU issue rate of the current device, the figure
+ * the roofline's peak rests on (a calibration for the bench, not a hashing call).  Every CU
+ * is filled with waves_per_simd workgroups of four waves; each wave runs long chains of one
+ * instruction kind over eight independent accumulators per lane, or, for the compression
+ * kinds, the library's own MD5 / SHA-1 / SM3 compression on register data with no memory
+ * traffic (plus one xor per block feeding the state back into the words).
+ *   kind            HB_PROBE_*: ADD3 v_add3_u32, ALIGNBIT v_alignbit_b32, BITOP3
+ *                   v_bitop3_b32, ADD v_add_u32 (VOP2), XOR v_xor_b32 (VOP2), XAD v_xad_u32,
+ *                   PERM v_perm_b32, MIX_ALT bitop3 and alignbit alternating, MIX_2_1 two
+ *                   bitop3 to one alignbit, MD5 / SHA1 / SM3 compressions
+ *   waves_per_simd  1..8
+ *   cycles_out      host: SIMD cycles per wave instruction (instruction kinds) or per wave
+ *                   and 64-byte block (compression kinds), best of three launches
+ *   clock_ghz_out   host, may be null: the engine clock the waves ran at
+ * Allocates a small device buffer, synchronises the device and frees the buffer: run it
+ * alone.  Returns HB_EINVAL for an unknown kind, waves_per_simd outside 1..8 or a null
+ * cycles_out, HB_EHIP on a HIP failure.
+ */
+enum { HB_PROBE_ADD3 = 0, HB_PROBE_ALIGNBIT = 1, HB_PROBE_BITOP3 = 2, HB_PROBE_ADD = 3, HB_PROBE_XOR = 4,
+       HB_PROBE_XAD = 5, HB_PROBE_PERM = 6, HB_PROBE_MIX_ALT = 7, HB_PROBE_MIX_2_1 = 8, HB_PROBE_MD5 = 9,
+       HB_PROBE_SHA1 = 10, HB_PROBE_SM3 = 11, HB_PROBE_KINDS = 12 };
+int hb_probe_valu(int kind, int waves_per_simd, double *cycles_out, double *clock_ghz_out);
+
+/*
  * hash_batch -- plain batch hashing, one GPU lane per message, in index order.
  *   algo         HB_MD5 / HB_SHA1 / HB_SM3
  *   messages     device, packed message bytes

@@ -19,7 +19,7 @@ LIB = PKG / "libhb.so"
 OBJDIR = PKG / "_build"
 
 SOURCES = ["hb_api.cpp", "hb_kernels.hip", "hb_stream.hip", "hb_plan.hip", "hb_serve.hip", "hb_host.cpp", "hb_server.cpp",
-           "hb_cpu.cpp"]
+           "hb_cpu.cpp", "hb_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HB_OFFLOAD_ARCH", "gfx950")

@@ -49,6 +49,8 @@ def lib() -> ctypes.CDLL:
         L.hb_last_error.restype = ctypes.c_char_p
         L.hb_device_info.argtypes = [ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                                      ctypes.c_char_p, ctypes.c_size_t]
+        if hasattr(L, "hb_probe_valu"):
+            L.hb_probe_valu.argtypes = [_i, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.hash_batch.argtypes = [_i, _vp, _vp, _vp, _u64, _vp, _vp]
         L.hash_batch_strided.argtypes = [_i, _vp, _vp, _vp, _u64, _vp, _u64, _vp]
         L.hash_batch_fixed.argtypes = [_i, _vp, _u64, _u64, _vp, _vp]
@@ -123,6 +125,19 @@ def device_info() -> dict:
     check(lib().hb_device_info(ctypes.byref(cu), ctypes.byref(ws), ctypes.byref(clk), name, 64))
     return {"cu_count": cu.value, "wave_size": ws.value, "clock_khz": clk.value,
             "arch": name.value.decode()}
+
+
+# hb_probe_valu kinds, in the order of include/hb.h
+PROBE_KINDS = ["add3", "alignbit", "bitop3", "add", "xor", "xad", "perm", "mix_bitop3_alignbit_1_1",
+               "mix_bitop3_alignbit_2_1", "md5", "sha1", "sm3"]
+
+
+def probe_valu(kind: str, waves_per_simd: int = 4) -> tuple[float, float]:
+    """SIMD cycles per wave instruction (per wave and block for the compression kinds) and
+    the engine clock in GHz, from hb_probe_valu."""
+    c, g = ctypes.c_double(), ctypes.c_double()
+    check(lib().hb_probe_valu(PROBE_KINDS.index(kind), waves_per_simd, ctypes.byref(c), ctypes.byref(g)))
+    return c.value, g.value
 
 
 # ---------------------------------------------------------------------------------------
