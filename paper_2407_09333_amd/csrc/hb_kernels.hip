@@ -68,16 +68,17 @@ constexpr int kCpolNonTemporal = 2;
 // and msg_len 4-byte aligned); the last one or two blocks and a partial last wave go through
 // the per-lane path.  The loads are buffer loads off one wave-uniform base, so they take no
 // vector address arithmetic (MD5 issues its compression instructions and almost nothing
-// more) and few registers: four or five waves per SIMD.  MD5, whose reads and compression
-// take about as long as each other, streams: non-temporal loads (every line is read once,
-// whole, by one instruction) with the next two bursts in flight.  SHA-1 and SM3 are bound by
-// their compression: cached loads, one burst ahead.  In interleaved runs on 2^20 x 1 KiB
-// against the per-lane kernel: MD5 0.905, SHA-1 0.984, SM3 0.981 of its time.
+// more) and few registers.  Each wave keeps the next burst in flight while it compresses the
+// current one.  MD5, whose reads and compression take about as long as each other, streams
+// with non-temporal loads (every line is read once, whole, by one instruction) at five waves
+// per SIMD, the most the LDS holds (8 KiB per wave); SHA-1 and SM3, bound by their
+// compression, use cached loads at five and four.  In interleaved runs on 2^20 x 1 KiB
+// against the per-lane kernel: MD5 0.92, SHA-1 0.98, SM3 0.98 of its time.
 template <int A>
-__global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
+__global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(A == MD5 ? 5 : 4))) void k_plain_lds(const uint8_t *__restrict__ msgs, uint64_t n,
                                                            uint64_t len, uint8_t *__restrict__ out)
 {
-    constexpr bool kStream = A == MD5;
+    constexpr bool kStream = A == MD5;  // non-temporal loads
     __shared__ u32x4 slice[kPlainBlock / 64][512];  // per wave: 64 messages x 128 bytes
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u), lane = threadIdx.x % 64u;
     const uint64_t m0 = (uint64_t(xcd_contiguous_block()) * (kPlainBlock / 64) + wave) * 64u;
@@ -146,49 +147,12 @@ __global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(4))
     };
     // A wave's LDS operations complete in order, so a burst's writes to the slice follow the
     // previous burst's reads of it.
-    if constexpr (kStream) {
-        // bursts k + 1 and k + 2 in flight while k is compressed.  The steady-state loop's
-        // loads are unconditional: a load under a branch makes the compiler's wait before a
-        // stage count it as possibly outstanding, so each loop top waited for both buffers
-        // and the second burst had only one burst of compression to arrive in.
-        u32x4 pa[8], pb[8];
-        if (nburst >= 2) {
-            load(pa, 0);
-            __builtin_amdgcn_sched_barrier(0);  // pa's loads issue before pb's, as in the loop
-            load(pb, 1);
-            uint64_t k = 0;
-            for (; k + 4 <= nburst; k += 2) {
-                stage(pa);
-                load(pa, k + 2);
-                burst();
-                stage(pb);
-                load(pb, k + 3);
-                burst();
-            }
-            // bursts k and k + 1 are in flight; at most one more remains
-            const bool odd = k + 3 == nburst;
-            stage(pa);
-            if (odd) load(pa, k + 2);
-            burst();
-            stage(pb);
-            burst();
-            if (odd) {
-                stage(pa);
-                burst();
-            }
-        } else if (nburst == 1) {
-            load(pa, 0);
-            stage(pa);
-            burst();
-        }
-    } else {
-        u32x4 pre[8];
-        if (nburst) load(pre, 0);
-        for (uint64_t k = 0; k < nburst; ++k) {
-            stage(pre);
-            if (k + 1 < nburst) load(pre, k + 1);
-            burst();
-        }
+    u32x4 pre[8];
+    if (nburst) load(pre, 0);
+    for (uint64_t k = 0; k < nburst; ++k) {
+        stage(pre);
+        if (k + 1 < nburst) load(pre, k + 1);
+        burst();
     }
     const uint64_t mi = m0 + lane;
     if (mi >= n) return;

@@ -48,8 +48,8 @@ def test_fixed_lengths(hb, algo, L):
 def test_fixed_lds_staged(hb, monkeypatch, algo, n, L):
     """The LDS-staged fixed-length kernel (the default; set explicitly): whole waves stage
     two blocks per burst through LDS, partial waves and the last blocks go per lane; burst
-    counts 0 to 9 and 16, odd and even, below and inside MD5's two-burst steady-state loop;
-    digests bit-exact against the oracle, and no write outside the digest buffer."""
+    counts 0 to 9 and 16, lengths with and without a padding-only last block; digests
+    bit-exact against the oracle, and no write outside the digest buffer."""
     monkeypatch.setenv("HB_PLAIN_LDS", "1")
     b = workloads.fixed_batch(algo, n, L, seed=500 + L)
     print(f"case fixed lds algo={algo} n={n} L={L}", flush=True)
