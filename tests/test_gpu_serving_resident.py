@@ -51,9 +51,15 @@ def test_resident_results_match_oracle_and_alone(hb, resident):
     srv.close()
 
 
-def test_resident_long_chains(hb, resident):
+@pytest.mark.parametrize("latency_items", [None, "0", "1000000"])
+def test_resident_long_chains(hb, resident, monkeypatch, latency_items):
+    """Requests holding long chains, with item formation as configured by default, never
+    cooperative (every item one message per lane) and always cooperative (each algorithm's
+    two longest classes of >= 128 blocks in items of <= 4 messages run by whole waves)."""
+    if latency_items is not None:
+        monkeypatch.setenv("HB_SERVER_RESIDENT_LATENCY_ITEMS", latency_items)
     reqs = _long_chain_requests(seed=62)
-    print("case resident long chains", flush=True)
+    print(f"case resident long chains latency_items={latency_items}", flush=True)
     srv = hb.Server(hbm_budget_bytes=1 << 30, max_slots=64)
     tickets = [srv.submit(r.messages, r.offsets, r.lengths, algo=r.algo, algos=r.algos) for r in reqs]
     for r, t in zip(reqs, tickets):
