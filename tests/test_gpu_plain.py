@@ -228,3 +228,25 @@ def test_full_size_fixed_1m_x_1024_all(hb, algo):
     host = b.messages.cpu().numpy()
     want = oracle.hash_batch(algo, host, b.offsets, b.lengths)
     assert_same(got.cpu().numpy(), want, "full fixed, every digest")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("L,n", [((1 << 25) - 4, 65), (1 << 25, 64)])
+def test_fixed_longest_messages_lds_limit(hb, algo, L, n):
+    """Fixed-length messages at the LDS-staged kernel's length limit: 2^25 - 4 bytes is the
+    longest it takes (the wave's 64 messages span 2^31 - 256 bytes, its buffer range; its
+    32-bit load offsets reach 1.9 GB), with a partial second wave; 2^25 bytes goes to the
+    per-lane kernel.  Every digest bit-exact against the oracle."""
+    import torch
+
+    msgs = workloads.host_random_bytes(n * L, seed=1300 + algo + (L & 7))
+    offs = np.arange(n, dtype=np.uint64) * np.uint64(L)
+    lens = np.full(n, L, np.uint64)
+    print(f"case fixed longest algo={algo} L={L} n={n}", flush=True)
+    dev = torch.from_numpy(msgs).cuda()
+    ds = oracle.DIGEST_SIZE[algo]
+    buf, out = guarded_out(n, ds)
+    hb.hash_batch_fixed(algo, dev, n, L, out=out)
+    check_guard(buf, n, ds)
+    del dev
+    assert_same(out.cpu().numpy(), oracle.hash_batch(algo, msgs, offs, lens), "fixed longest")
